@@ -1,0 +1,211 @@
+/*
+ * pint.h -- C ABI of the MI355X (gfx950) all-at-once space-time solver for
+ * the fourth-order problems of Garai & Mandal, "Diagonalization based
+ * parallel-in-time method for a class of fourth order time dependent PDEs"
+ * (arXiv:2304.14021).
+ *
+ * Problems (homogeneous Neumann conditions, unit interval or unit square):
+ *   biharmonic heat   u_t = -Lap^2 u                          (Section 2, eq. modelproblem1a)
+ *   linearized CH     u_t = -beta^2 Lap u - eps^2 Lap^2 u      (Section 3, eq. modelproblem2a)
+ *   nonlinear CH      u_t = Lap(u^3 - u) - eps^2 Lap^2 u       (Section 4, eq. modelproblem3)
+ * discretized by the cell-centred Neumann Laplacian (N cells, h = L/N,
+ * x_j = (j + 1/2) h) and the theta-method / backward Euler / Eyre splitting in
+ * time (eqs. linear-theta1, fully-dis_CH, fully-dis_CH_WR_Eyre).
+ *
+ * The solve is the paper's waveform-relaxation / quasi-Newton iteration with
+ * the periodic-like initial condition u(0) = alpha u(T) - alpha u^{k-1}(T) + u0
+ * (eqs. modelproblem1a_wr, modelproblem3_wr), written in correction form
+ * U <- U + P_alpha^{-1} r(U), where r is the alpha = 0 all-at-once residual
+ * evaluated in FP64 and P_alpha is the Strang-type alpha-circulant space-time
+ * matrix, inverted by the three steps of eq. pintiter1 / pintiter_CH:
+ * time transform (F Gamma_alpha (x) I), N_t independent shifted spatial solves
+ * (diagonalized by the 2D DCT-II), inverse time transform.
+ *
+ * Conventions for every entry point
+ *  - All functions return int: PINT_OK (0) or a negative PINT_E* code.  No C++
+ *    exception crosses the ABI.  pint_status_string() names a code;
+ *    pint_plan_last_error() gives the message of the last failing call on a
+ *    plan, pint_last_error() that of the last failing call on this thread.
+ *  - "d_" pointers are device memory on the current HIP device, owned by the
+ *    caller, never freed by the library.  "h_" pointers are host memory.
+ *  - Space-time arrays are FP64, layout [N_t][N_y][N_x] row-major (x fastest),
+ *    holding u_1 .. u_{N_t}; the datum u_0 is a separate [N_y][N_x] array.
+ *    In 1D, N_y = 1.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue work on it and return; pint_solve() synchronizes with the
+ *    stream to read its convergence control (see there).
+ *  - A plan may be used by one host thread at a time.  Calls on different
+ *    plans are independent.
+ *  - Sizes: N (cells per dimension) a power of two in [8, 512]; N_t a power of
+ *    two in [4, 1024].  Other sizes return PINT_EINVAL.
+ */
+#ifndef PINT_H
+#define PINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define PINT_OK            0
+#define PINT_EINVAL       (-1)  /* invalid argument or unsupported size       */
+#define PINT_ENOCONV      (-2)  /* max_iter reached before the stop rule held  */
+#define PINT_EDIVERGED    (-3)  /* NaN/Inf or growing updates detected         */
+#define PINT_ENOMEM       (-4)  /* workspace/pool too small                    */
+#define PINT_EHIP         (-5)  /* a HIP runtime call failed                   */
+#define PINT_ETIMEDOUT    (-6)  /* server wait timed out                       */
+#define PINT_ECANCELED    (-7)  /* server request cancelled                    */
+#define PINT_ENOTFOUND    (-8)  /* unknown server ticket                       */
+
+/* ------------------------------------------------------------- operators */
+#define PINT_OP_BIHARMONIC 0    /* A = Lap_h^2                                 */
+#define PINT_OP_LINEAR_CH  1    /* A = beta^2 Lap_h + eps^2 Lap_h^2            */
+#define PINT_OP_CH         2    /* nonlinear CH, fully implicit BE (PinT-I)    */
+#define PINT_OP_CH_EYRE    3    /* nonlinear CH, Eyre splitting (PinT-II)      */
+
+/* ------------------------------------------------------------- precision */
+#define PINT_PREC_FP64          0  /* every stage in FP64                      */
+#define PINT_PREC_FP32_REFINE   1  /* transforms/divide FP32, residual+update FP64 */
+#define PINT_PREC_FP32_NOREFINE 2  /* residual and update in FP32 too          */
+#define PINT_PREC_BF16_REFINE   3  /* dense time contraction with BF16 operands,
+                                      FP32 accumulate; residual+update FP64    */
+
+/* ------------------------------------------------------------- time path */
+#define PINT_TIME_AUTO  0          /* FFT over time (alpha-circulant)          */
+#define PINT_TIME_FFT   1          /* batched FFT over the time index          */
+#define PINT_TIME_DENSE 2          /* dense contraction over the time index on
+                                      the matrix cores (FP32 or BF16 MFMA)     */
+
+/* ----------------------------------------------------------------- flags */
+#define PINT_FLAG_INIT_BROADCAST_U0 0x1u /* fill d_U with u0 before iterating */
+#define PINT_FLAG_STAGE_TIMING      0x2u /* fill pint_report.ms_stage (adds syncs) */
+
+#define PINT_HIST 64
+
+/* Statement of one problem (plain data, versioned by struct_size). */
+typedef struct pint_problem {
+  size_t struct_size;  /* sizeof(pint_problem)                                 */
+  int op;              /* PINT_OP_*                                            */
+  int dim;             /* 1 or 2                                               */
+  int nx, ny;          /* cells per dimension (ny = 1 in 1D; nx == ny in 2D)   */
+  int nt;              /* number of unknown time levels; T = nt * dt           */
+  double lx, ly;       /* domain lengths (h = lx / nx); 0 means 1.0            */
+  double dt;           /* time step > 0                                        */
+  double theta;        /* 1 (backward Euler) or 0.5 (trapezoidal); linear ops  */
+  double eps;          /* interface parameter epsilon > 0 (ignored: biharmonic)*/
+  double beta;         /* linearized CH parameter (ignored unless LINEAR_CH)   */
+  double alpha;        /* PinT parameter in (0, 1); 0 = choose automatically   */
+  int precision;       /* PINT_PREC_*                                          */
+  int time_path;       /* PINT_TIME_*                                          */
+  double rtol;         /* target relative error (L^inf(L^2)); 0 = 1e-10        */
+  int max_iter;        /* cap on outer iterations (<= PINT_HIST); 0 = 30       */
+  unsigned flags;      /* PINT_FLAG_*                                          */
+} pint_problem;
+
+/* Outcome of one solve (filled by the library when a pointer is passed). */
+typedef struct pint_report {
+  size_t struct_size;          /* sizeof(pint_report), set by the caller       */
+  int status;                  /* same as the return code of pint_solve         */
+  int iterations;              /* outer iterations performed                    */
+  double alpha_used;           /* alpha actually used                           */
+  double c_bar;                /* final scalar averaged Jacobian (CH ops)        */
+  double est_rel_err;          /* error estimate rho/(1-rho) * |dU|/|U|          */
+  double res_hist[PINT_HIST];  /* max_n ||r_n||_2 of the iterate entering step k */
+  double upd_hist[PINT_HIST];  /* max_n ||delta_n||_2 / max_n ||u_n||_2, step k */
+  double ms_stage[8];          /* residual+DCT, time solve, IDCT+update, control,
+                                  (FLAG_STAGE_TIMING only), then unused        */
+  double ms_total;             /* wall time of the solve call (host clock)      */
+} pint_report;
+
+typedef struct pint_plan pint_plan;
+
+/* Returns a static string naming a status code. */
+const char* pint_status_string(int status);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* pint_last_error(void);
+/* Library version string. */
+const char* pint_version(void);
+
+/*
+ * Validate a problem and build its plan: FP64 constant tables (a = alpha^(1/N_t),
+ * a^j, the time eigenvalues lambda_{1,l} = (1 - a w^l)/dt and
+ * lambda_{2,l} = theta + (1 - theta) a w^l with w = exp(-2 pi i / N_t)
+ * (Section 2.1, Lemma and eq. pintiter1), the 1D Laplacian spectrum
+ * (2/h^2)(cos(k pi/N) - 1), FFT twiddles), copied to the current device.
+ * alpha == 0 selects alpha automatically (1e-3, reduced until
+ * alpha * R^{N_t} <= 0.1 with R^{N_t} = (1 + dt mu_min)^{-N_t}, the
+ * admissibility of thm3/thm6); an explicit alpha with alpha * R^{N_t} >= 1/2
+ * is rejected with PINT_EINVAL.  The plan owns its small device tables
+ * (< 1 MB); bulk memory is the caller's workspace.  *out receives the plan.
+ */
+int pint_plan_create(const pint_problem* p, pint_plan** out);
+/* Free a plan and its device tables.  NULL is accepted. */
+int pint_plan_destroy(pint_plan* plan);
+/* Message of the last failing call on this plan. */
+const char* pint_plan_last_error(const pint_plan* plan);
+/* Bytes of device workspace pint_solve and the stage calls need. */
+int pint_plan_workspace_size(const pint_plan* plan, size_t* bytes);
+/* alpha the plan uses (after automatic choice). */
+int pint_plan_alpha(const pint_plan* plan, double* alpha);
+
+/*
+ * Full solve: runs the outer iteration (residual, forward DCT-II, time
+ * transform + shifted divide + inverse, inverse DCT + FP64 update, reductions
+ * and stop rule) until the estimated relative error is below rtol or
+ * max_iter is reached.
+ *   d_u0    [N_y][N_x] FP64 initial datum u_0.
+ *   d_U     [N_t][N_y][N_x] FP64, initial guess on entry (or filled from u0
+ *           with PINT_FLAG_INIT_BROADCAST_U0), solution on exit.  Also written
+ *           when PINT_ENOCONV / PINT_EDIVERGED are returned.
+ *   d_work  device workspace of >= pint_plan_workspace_size bytes, 256-byte
+ *           aligned; contents on entry are ignored.
+ *   rep     optional report (NULL allowed); rep->struct_size must be set.
+ * The call enqueues on `stream` and synchronizes with it once per outer
+ * iteration to read the 4-byte stop flag; it returns after the last iteration
+ * has completed on the device.
+ */
+int pint_solve(pint_plan* plan, const double* d_u0, double* d_U, void* d_work, size_t work_bytes,
+               void* stream, pint_report* rep);
+
+/* ---- stage entry points (same kernels as pint_solve; used for per-stage parity) ----
+ * Working precision W: double for PINT_PREC_FP64, float otherwise.  d_work must
+ * be a workspace as for pint_solve.  All are asynchronous on `stream`.
+ */
+
+/* a1 (+ a2): true alpha = 0 all-at-once residual r = b_0 - K(U) of the plan's
+ * operator (eqs. all-at-once1 / nonlinear_G / nonlinear_Q with alpha = 0),
+ * FP64 arithmetic, written as FP64 [N_t][N_y][N_x] into d_r (no transform). */
+int pint_residual(pint_plan* plan, const double* d_u0, const double* d_U, double* d_r,
+                  void* d_work, size_t work_bytes, void* stream);
+
+/* a2: orthonormal 2D (1D if dim = 1) DCT-II of each of the N_t slices of
+ * d_in (type W, [N_t][N_y][N_x]) into d_out (type W, [N_t][k_y][k_x]);
+ * d_in == d_out allowed.  inverse != 0 applies the inverse (DCT-III). */
+int pint_dct(pint_plan* plan, const void* d_in, void* d_out, int inverse, void* stream);
+
+/* a3-a5: for each spatial cosine mode k, y = Gamma^{-1} F^{-1} D^{-1} F Gamma x
+ * over the time index: the alpha-circulant space-time solve in the DCT basis
+ * (Section 2.1, eq. pintiter1 Steps 1-3; CH: eq. pintiter_CH), in place on
+ * d_S (type W, [N_t][k_y][k_x]).  c_bar is the scalar averaged Jacobian used
+ * by the CH operators (ignored for linear ones). */
+int pint_time_solve(pint_plan* plan, void* d_S, double c_bar, void* stream);
+
+/* a2-a6 without the update: d_delta = P_alpha^{-1} d_r for an FP64 residual
+ * d_r [N_t][N_y][N_x] (read) into FP64 d_delta (written), through the
+ * working-precision DCT and time solve. */
+int pint_precond_apply(pint_plan* plan, const double* d_r, double* d_delta, double c_bar,
+                       void* d_work, size_t work_bytes, void* stream);
+
+/* Diagnostics of a space-time state: per-level discrete mass h^d sum u and
+ * Ginzburg-Landau energy h^d [sum (u^2-1)^2/4 + eps^2/2 sum_faces ((u'-u)/h)^2]
+ * (Section 1), FP64, written to device arrays d_mass[N_t], d_energy[N_t]. */
+int pint_diagnostics(pint_plan* plan, const double* d_U, double* d_mass, double* d_energy,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINT_H */

@@ -223,13 +223,13 @@ def spatial_symbols(p, c_bar: float = 0.0):
     return lam, mu
 
 
-def precond_solve_modal(p, r: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
-    """delta = P_alpha^{-1} r, with the spatial operator diagonalized by the
-    explicit orthonormal cosine matrix and one dense N_t x N_t alpha-circulant
-    solve per spatial mode (numpy.linalg.solve).  Same result as
-    ``precond_solve``; usable at moderate sizes."""
+def time_solve_modal(p, rh: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
+    """The space-time solve in the cosine basis: for each spatial mode k the
+    dense N_t x N_t alpha-circulant system (C1 + mu_k C2) y = x (linear), or
+    its CH forms, solved by numpy.linalg.solve.  rh is [N_t][modes...] (DCT
+    coefficients); returns the same shape."""
     nt = p.nt
-    rh = dct2(r, p.dim).reshape(nt, -1)          # [nt][modes]
+    x = rh.reshape(nt, -1)
     lam, mu = spatial_symbols(p)
     c1, c2 = circulant_blocks(nt, p.dt, p.theta if p.op in ("biharmonic", "linear_ch") else 1.0, p.alpha)
     if p.op in ("biharmonic", "linear_ch"):
@@ -242,8 +242,16 @@ def precond_solve_modal(p, r: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
                 + lam[:, None, None] * c3[None])
     else:
         raise ValueError(p.op)
-    sol = np.linalg.solve(mats, rh.T[:, :, None])[:, :, 0]   # [modes][nt]
-    return idct2(sol.T.reshape(r.shape), p.dim)
+    sol = np.linalg.solve(mats, x.T[:, :, None])[:, :, 0]   # [modes][nt]
+    return sol.T.reshape(rh.shape)
+
+
+def precond_solve_modal(p, r: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
+    """delta = P_alpha^{-1} r, with the spatial operator diagonalized by the
+    explicit orthonormal cosine matrix and one dense N_t x N_t alpha-circulant
+    solve per spatial mode (``time_solve_modal``).  Same result as
+    ``precond_solve``; usable at moderate sizes."""
+    return idct2(time_solve_modal(p, dct2(r, p.dim), c_bar), p.dim)
 
 
 # ------------------------------------------------------------ outer iteration

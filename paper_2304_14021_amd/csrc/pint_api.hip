@@ -1,0 +1,599 @@
+// Host runtime and C ABI: plan construction (FP64 constant tables, alpha
+// choice), workspace layout, the outer iteration loop and the stage entry
+// points.  Everything on the hot path runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pint.h"
+#include "pint_kernels.hpp"
+
+using namespace pint;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_err(std::string* plan_err, int code, const std::string& msg) {
+  g_last_error = msg;
+  if (plan_err) *plan_err = msg;
+  return code;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct pint_plan {
+  pint_problem p;
+  int dim, n, nt, ns;
+  double h, alpha, a, dof, rtol;
+  int max_iter;
+  bool fp64;  // working precision W = double
+  std::string err;
+
+  // device tables (one allocation), FP64 then FP32 copies
+  void* d_tab = nullptr;
+  size_t tab_bytes = 0;
+  DctTables<double> dtd{};
+  DctTables<float> dtf{};
+  TimeArgs<double> tad{};
+  TimeArgs<float> taf{};
+  ResidArgs ra{};
+
+  int* h_flag = nullptr;  // pinned 4-byte stop flag readback
+  std::vector<hipEvent_t> ev;
+
+  ~pint_plan() {
+    if (d_tab) (void)hipFree(d_tab);
+    if (h_flag) (void)hipHostFree(h_flag);
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+struct HostTables {
+  std::vector<std::complex<double>> tw_s, wq, wi, tw_t, lam1, pco, qco;
+  std::vector<double> aj, aij, lamx, lamy;
+};
+
+double spectrum(int k, int n, double h) { return (2.0 / (h * h)) * (std::cos(M_PI * k / n) - 1.0); }
+
+// Smallest eigenvalue of the spatial part of the preconditioned operator
+// (A for the linear operators; Lap_h + eps^2 Lap_h^2 for CH with c_bar = 0).
+double mu_min(const pint_problem& p, int dim, int n, double h) {
+  double best = 0.0;
+  const int ny = dim == 2 ? n : 1;
+  for (int ky = 0; ky < ny; ++ky)
+    for (int kx = 0; kx < n; ++kx) {
+      const double lam = spectrum(kx, n, h) + (dim == 2 ? spectrum(ky, n, h) : 0.0);
+      double mu;
+      switch (p.op) {
+        case PINT_OP_BIHARMONIC: mu = lam * lam; break;
+        case PINT_OP_LINEAR_CH: mu = p.beta * p.beta * lam + p.eps * p.eps * lam * lam; break;
+        case PINT_OP_CH: mu = lam + p.eps * p.eps * lam * lam; break;
+        default: mu = p.eps * p.eps * lam * lam; break;  // Eyre: implicit part only
+      }
+      if (mu < best) best = mu;
+    }
+  return best;
+}
+
+int validate(const pint_problem* p, std::string* err) {
+  if (!p) return set_err(err, PINT_EINVAL, "problem is NULL");
+  if (p->struct_size < sizeof(pint_problem)) return set_err(err, PINT_EINVAL, "pint_problem.struct_size too small");
+  if (p->op < PINT_OP_BIHARMONIC || p->op > PINT_OP_CH_EYRE) return set_err(err, PINT_EINVAL, "unknown op");
+  if (p->dim != 1 && p->dim != 2) return set_err(err, PINT_EINVAL, "dim must be 1 or 2");
+  if (!is_pow2(p->nx) || p->nx < 8 || p->nx > 512)
+    return set_err(err, PINT_EINVAL, "nx must be a power of two in [8, 512]");
+  if (p->dim == 2 && p->ny != p->nx) return set_err(err, PINT_EINVAL, "2D grids must be square (ny == nx)");
+  if (p->dim == 2 && p->nx > 128) return set_err(err, PINT_EINVAL, "2D grids above 128^2 are not built yet");
+  if (p->dim == 1 && p->ny != 1 && p->ny != 0) return set_err(err, PINT_EINVAL, "1D problems need ny == 1");
+  if (!is_pow2(p->nt) || p->nt < 4 || p->nt > 1024)
+    return set_err(err, PINT_EINVAL, "nt must be a power of two in [4, 1024]");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return set_err(err, PINT_EINVAL, "dt must be > 0");
+  const bool linear = p->op == PINT_OP_BIHARMONIC || p->op == PINT_OP_LINEAR_CH;
+  if (linear && !(p->theta == 1.0 || p->theta == 0.5)) return set_err(err, PINT_EINVAL, "theta must be 1 or 0.5");
+  if (!linear && p->theta != 1.0 && p->theta != 0.0)
+    return set_err(err, PINT_EINVAL, "the CH schemes are backward Euler (theta = 1)");
+  if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
+  if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
+  if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE)
+    return set_err(err, PINT_EINVAL, "precision not supported by this build");
+  if (p->time_path != PINT_TIME_AUTO && p->time_path != PINT_TIME_FFT)
+    return set_err(err, PINT_EINVAL, "time path not supported by this build");
+  if (p->max_iter < 0 || p->max_iter > PINT_HIST) return set_err(err, PINT_EINVAL, "max_iter must be in [0, 64]");
+  if (p->rtol < 0.0) return set_err(err, PINT_EINVAL, "rtol must be >= 0");
+  const double lx = p->lx > 0 ? p->lx : 1.0;
+  if (!std::isfinite(lx)) return set_err(err, PINT_EINVAL, "lx must be finite");
+  return PINT_OK;
+}
+
+void build_tables(pint_plan* pl, HostTables& t) {
+  const int n = pl->n, nt = pl->nt;
+  const double h = pl->h, dt = pl->p.dt, a = pl->a, th = pl->p.theta;
+  const double la = std::log(pl->alpha) / nt;  // log a
+  t.tw_s.resize(n);
+  t.wq.resize(n);
+  t.wi.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = -2.0 * M_PI * m / n;
+    t.tw_s[m] = {std::cos(ang), std::sin(ang)};
+    const double s = m == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+    const double q = M_PI * m / (2.0 * n);
+    t.wq[m] = s * std::complex<double>(std::cos(q), -std::sin(q));
+    t.wi[m] = std::complex<double>(std::cos(q), std::sin(q)) / s;
+  }
+  t.tw_t.resize(nt);
+  t.lam1.resize(nt);
+  t.pco.resize(nt);
+  t.qco.resize(nt);
+  t.aj.resize(nt);
+  t.aij.resize(nt);
+  const double e2 = pl->p.eps * pl->p.eps, b2 = pl->p.beta * pl->p.beta;
+  for (int l = 0; l < nt; ++l) {
+    const double ang = -2.0 * M_PI * l / nt;
+    const std::complex<double> w(std::cos(ang), std::sin(ang));
+    t.tw_t[l] = w;
+    // Time eigenvalues of the alpha-circulant blocks (Lemma of Section 2.1)
+    // in the exp(-2 pi i l / N_t) ordering of the forward FFT.
+    t.lam1[l] = (1.0 - a * w) / dt;
+    const std::complex<double> lam2 = th + (1.0 - th) * a * w;
+    switch (pl->p.op) {
+      case PINT_OP_BIHARMONIC:
+        t.pco[l] = 0.0;
+        t.qco[l] = lam2;
+        break;
+      case PINT_OP_LINEAR_CH:
+        t.pco[l] = b2 * lam2;
+        t.qco[l] = e2 * lam2;
+        break;
+      case PINT_OP_CH:  // lambda1 + (1 - c_bar) lam + eps^2 lam^2 (eq. pintiter_CH)
+        t.pco[l] = 1.0;
+        t.qco[l] = e2;
+        break;
+      default:  // Eyre: lambda1 + (lambda3 - c_bar) lam + eps^2 lam^2 (eq. pintiter_CH_eyre)
+        t.pco[l] = a * w;
+        t.qco[l] = e2;
+        break;
+    }
+    t.aj[l] = std::exp(la * l);
+    t.aij[l] = std::exp(-la * l) / nt;
+  }
+  t.lamx.resize(n);
+  for (int k = 0; k < n; ++k) t.lamx[k] = spectrum(k, n, h);
+  if (pl->dim == 2) {
+    t.lamy = t.lamx;
+  } else {
+    t.lamy.assign(1, 0.0);
+  }
+}
+
+template <typename T>
+size_t put_cx(std::vector<unsigned char>& buf, size_t off, const std::vector<std::complex<double>>& v) {
+  off = align256(off);
+  buf.resize(off + v.size() * 2 * sizeof(T));
+  T* d = reinterpret_cast<T*>(buf.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) {
+    d[2 * i] = T(v[i].real());
+    d[2 * i + 1] = T(v[i].imag());
+  }
+  return off;
+}
+template <typename T>
+size_t put_re(std::vector<unsigned char>& buf, size_t off, const std::vector<double>& v) {
+  off = align256(off);
+  buf.resize(off + v.size() * sizeof(T));
+  T* d = reinterpret_cast<T*>(buf.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) d[i] = T(v[i]);
+  return off;
+}
+
+struct Offs {
+  size_t tw_s, wq, wi, tw_t, lam1, pco, qco, aj, aij, lamx, lamy;
+};
+
+template <typename T>
+Offs put_all(std::vector<unsigned char>& buf, const HostTables& t) {
+  Offs o;
+  o.tw_s = put_cx<T>(buf, buf.size(), t.tw_s);
+  o.wq = put_cx<T>(buf, buf.size(), t.wq);
+  o.wi = put_cx<T>(buf, buf.size(), t.wi);
+  o.tw_t = put_cx<T>(buf, buf.size(), t.tw_t);
+  o.lam1 = put_cx<T>(buf, buf.size(), t.lam1);
+  o.pco = put_cx<T>(buf, buf.size(), t.pco);
+  o.qco = put_cx<T>(buf, buf.size(), t.qco);
+  o.aj = put_re<T>(buf, buf.size(), t.aj);
+  o.aij = put_re<T>(buf, buf.size(), t.aij);
+  o.lamx = put_re<T>(buf, buf.size(), t.lamx);
+  o.lamy = put_re<T>(buf, buf.size(), t.lamy);
+  return o;
+}
+
+template <typename T>
+void bind(const Offs& o, unsigned char* base, const pint_plan* pl, DctTables<T>& dt, TimeArgs<T>& ta) {
+  dt.tw = reinterpret_cast<const cx<T>*>(base + o.tw_s);
+  dt.wq = reinterpret_cast<const cx<T>*>(base + o.wq);
+  dt.wi = reinterpret_cast<const cx<T>*>(base + o.wi);
+  ta.tw = reinterpret_cast<const cx<T>*>(base + o.tw_t);
+  ta.lam1 = reinterpret_cast<const cx<T>*>(base + o.lam1);
+  ta.pco = reinterpret_cast<const cx<T>*>(base + o.pco);
+  ta.qco = reinterpret_cast<const cx<T>*>(base + o.qco);
+  ta.aj = reinterpret_cast<const T*>(base + o.aj);
+  ta.aij = reinterpret_cast<const T*>(base + o.aij);
+  ta.lamx = reinterpret_cast<const T*>(base + o.lamx);
+  ta.lamy = reinterpret_cast<const T*>(base + o.lamy);
+  ta.nx = pl->n;
+  ta.ns = pl->ns;
+  ta.cbar_mode = (pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE) ? 1 : 0;
+  ta.cbar = nullptr;
+  ta.done = nullptr;
+}
+
+struct Work {
+  void* S;
+  double* part;
+  Ctrl* ctrl;
+};
+
+size_t work_size(const pint_plan* pl) {
+  const size_t wb = pl->fp64 ? 8 : 4;
+  return align256((size_t)pl->nt * pl->ns * wb) + align256((size_t)pl->nt * PART_STRIDE * 8) +
+         align256(sizeof(Ctrl));
+}
+
+int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
+  if (!d_work) return set_err(&pl->err, PINT_EINVAL, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return set_err(&pl->err, PINT_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < work_size(pl)) return set_err(&pl->err, PINT_ENOMEM, "workspace smaller than pint_plan_workspace_size");
+  const size_t wb = pl->fp64 ? 8 : 4;
+  unsigned char* b = static_cast<unsigned char*>(d_work);
+  w.S = b;
+  b += align256((size_t)pl->nt * pl->ns * wb);
+  w.part = reinterpret_cast<double*>(b);
+  b += align256((size_t)pl->nt * PART_STRIDE * 8);
+  w.ctrl = reinterpret_cast<Ctrl*>(b);
+  return PINT_OK;
+}
+
+int hip_fail(pint_plan* pl, hipError_t e, const char* what) {
+  return set_err(pl ? &pl->err : nullptr, PINT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                          \
+  do {                                              \
+    hipError_t e__ = (expr);                        \
+    if (e__ != hipSuccess) return hip_fail(pl, e__, what); \
+  } while (0)
+
+// Enqueue one outer iteration.
+template <typename T>
+int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st,
+                      hipEvent_t* evs) {
+  const DctTables<T>& dt = *reinterpret_cast<const DctTables<T>*>(pl->fp64 ? (void*)&pl->dtd : (void*)&pl->dtf);
+  TimeArgs<T> ta = *reinterpret_cast<const TimeArgs<T>*>(pl->fp64 ? (void*)&pl->tad : (void*)&pl->taf);
+  ta.cbar = &w.ctrl->c_bar;
+  ta.done = &w.ctrl->done;
+  ResidArgs ra = pl->ra;
+  ra.u0 = d_u0;
+  ra.U = d_U;
+  ra.part = w.part;
+  ra.done = &w.ctrl->done;
+  UpdArgs ua{d_U, w.part, &w.ctrl->done};
+  FinArgs fa{w.ctrl, w.part, pl->nt, pl->max_iter, pl->dof, pl->rtol};
+  T* S = static_cast<T*>(w.S);
+  if (evs) HIPCHK(hipEventRecord(evs[0], st), "hipEventRecord");
+  HIPCHK(launch_resid<T>(pl->dim, pl->n, ra, S, nullptr, dt, pl->nt, 0, st), "residual kernel");
+  if (evs) HIPCHK(hipEventRecord(evs[1], st), "hipEventRecord");
+  HIPCHK(launch_time<T>(pl->nt, S, ta, st), "time-solve kernel");
+  if (evs) HIPCHK(hipEventRecord(evs[2], st), "hipEventRecord");
+  HIPCHK(launch_update<T>(pl->dim, pl->n, ua, S, nullptr, dt, pl->nt, 0, st), "update kernel");
+  if (evs) HIPCHK(hipEventRecord(evs[3], st), "hipEventRecord");
+  HIPCHK(launch_finalize(fa, st), "finalize kernel");
+  if (evs) HIPCHK(hipEventRecord(evs[4], st), "hipEventRecord");
+  return PINT_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* pint_status_string(int s) {
+  switch (s) {
+    case PINT_OK: return "PINT_OK";
+    case PINT_EINVAL: return "PINT_EINVAL: invalid argument";
+    case PINT_ENOCONV: return "PINT_ENOCONV: not converged within max_iter";
+    case PINT_EDIVERGED: return "PINT_EDIVERGED: iteration diverged";
+    case PINT_ENOMEM: return "PINT_ENOMEM: workspace or pool too small";
+    case PINT_EHIP: return "PINT_EHIP: HIP runtime error";
+    case PINT_ETIMEDOUT: return "PINT_ETIMEDOUT: timed out";
+    case PINT_ECANCELED: return "PINT_ECANCELED: cancelled";
+    case PINT_ENOTFOUND: return "PINT_ENOTFOUND: unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+const char* pint_last_error(void) { return g_last_error.c_str(); }
+const char* pint_version(void) { return "pint-mi355x 0.1 (gfx950)"; }
+
+int pint_plan_create(const pint_problem* p, pint_plan** out) {
+  if (!out) return set_err(nullptr, PINT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p, nullptr);
+  if (rc) return rc;
+  pint_plan* pl = new (std::nothrow) pint_plan();
+  if (!pl) return set_err(nullptr, PINT_ENOMEM, "host allocation failed");
+  pl->p = *p;
+  pl->p.struct_size = sizeof(pint_problem);
+  pl->dim = p->dim;
+  pl->n = p->nx;
+  pl->nt = p->nt;
+  pl->ns = p->dim == 2 ? p->nx * p->nx : p->nx;
+  const double lx = p->lx > 0 ? p->lx : 1.0;
+  pl->h = lx / p->nx;
+  pl->dof = double(pl->ns) * pl->nt;
+  pl->rtol = p->rtol > 0 ? p->rtol : 1e-10;
+  pl->max_iter = p->max_iter > 0 ? p->max_iter : 30;
+  pl->fp64 = p->precision == PINT_PREC_FP64;
+  if (p->op == PINT_OP_CH || p->op == PINT_OP_CH_EYRE) pl->p.theta = 1.0;
+
+  // Admissibility of alpha: the slowest-decaying (or fastest-growing) mode
+  // multiplies the WR error by alpha R^{N_t} / (1 - alpha R^{N_t}) per sweep
+  // (fully discrete analysis of Section 2.2, thm3; thm6 for the spinodal
+  // case), R = R_theta(dt mu_min).  Require alpha R^{N_t} < 1/2.
+  const double mmin = mu_min(pl->p, pl->dim, pl->n, pl->h);
+  const double z = p->dt * mmin;
+  const double th = pl->p.theta;
+  const double R = (1.0 - (1.0 - th) * z) / (1.0 + th * z);
+  if (!(1.0 + th * z > 0.0)) {
+    delete pl;
+    return set_err(nullptr, PINT_EINVAL, "1 + theta dt mu_min <= 0: the sequential scheme is singular");
+  }
+  const double RN = std::pow(std::fabs(R) > 1.0 ? std::fabs(R) : 1.0, pl->nt);
+  if (p->alpha == 0.0) {
+    double al = 1e-3;
+    if (al * RN > 0.1) al = 0.1 / RN;
+    pl->alpha = al;
+  } else {
+    if (p->alpha * RN >= 0.5) {
+      delete pl;
+      return set_err(nullptr, PINT_EINVAL,
+                     "alpha * R^Nt >= 1/2: alpha is not admissible for this problem (choose alpha = 0 for auto)");
+    }
+    pl->alpha = p->alpha;
+  }
+  pl->p.alpha = pl->alpha;
+  pl->a = std::exp(std::log(pl->alpha) / pl->nt);
+
+  // residual coefficients
+  ResidArgs& ra = pl->ra;
+  ra.inv_dt = 1.0 / p->dt;
+  ra.inv_h2 = 1.0 / (pl->h * pl->h);
+  ra.theta = pl->p.theta;
+  const double e2 = p->eps * p->eps;
+  switch (p->op) {
+    case PINT_OP_BIHARMONIC: ra.c3 = 0; ra.c1 = 0; ra.c1p = 0; ra.c2 = -1.0; break;
+    case PINT_OP_LINEAR_CH: ra.c3 = 0; ra.c1 = -p->beta * p->beta; ra.c1p = 0; ra.c2 = -e2; break;
+    case PINT_OP_CH: ra.c3 = 1; ra.c1 = -1.0; ra.c1p = 0; ra.c2 = -e2; break;
+    default: ra.c3 = 1; ra.c1 = 0; ra.c1p = -1.0; ra.c2 = -e2; break;
+  }
+
+  HostTables t;
+  build_tables(pl, t);
+  std::vector<unsigned char> buf;
+  Offs od = put_all<double>(buf, t);
+  Offs of = put_all<float>(buf, t);
+  pl->tab_bytes = align256(buf.size());
+  hipError_t e = hipMalloc(&pl->d_tab, pl->tab_bytes);
+  if (e != hipSuccess) {
+    rc = hip_fail(nullptr, e, "hipMalloc(tables)");
+    delete pl;
+    return rc;
+  }
+  e = hipMemcpy(pl->d_tab, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rc = hip_fail(nullptr, e, "hipMemcpy(tables)");
+    delete pl;
+    return rc;
+  }
+  unsigned char* base = static_cast<unsigned char*>(pl->d_tab);
+  bind<double>(od, base, pl, pl->dtd, pl->tad);
+  bind<float>(of, base, pl, pl->dtf, pl->taf);
+  e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_flag), sizeof(int) * 4, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    rc = hip_fail(nullptr, e, "hipHostMalloc(flag)");
+    delete pl;
+    return rc;
+  }
+  *out = pl;
+  return PINT_OK;
+}
+
+int pint_plan_destroy(pint_plan* plan) {
+  delete plan;
+  return PINT_OK;
+}
+
+const char* pint_plan_last_error(const pint_plan* plan) { return plan ? plan->err.c_str() : ""; }
+
+int pint_plan_workspace_size(const pint_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return set_err(nullptr, PINT_EINVAL, "NULL argument");
+  *bytes = work_size(plan);
+  return PINT_OK;
+}
+
+int pint_plan_alpha(const pint_plan* plan, double* alpha) {
+  if (!plan || !alpha) return set_err(nullptr, PINT_EINVAL, "NULL argument");
+  *alpha = plan->alpha;
+  return PINT_OK;
+}
+
+int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, size_t work_bytes, void* stream,
+               pint_report* rep) {
+  if (!pl) return set_err(nullptr, PINT_EINVAL, "plan is NULL");
+  if (!d_u0 || !d_U) return set_err(&pl->err, PINT_EINVAL, "u0/U pointer is NULL");
+  if (rep && rep->struct_size < sizeof(pint_report))
+    return set_err(&pl->err, PINT_EINVAL, "pint_report.struct_size too small");
+  auto t0 = std::chrono::steady_clock::now();
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool timing = (pl->p.flags & PINT_FLAG_STAGE_TIMING) != 0;
+  if (timing && pl->ev.size() < size_t(5 * pl->max_iter)) {
+    while (pl->ev.size() < size_t(5 * pl->max_iter)) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e), "hipEventCreate");
+      pl->ev.push_back(e);
+    }
+  }
+  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) ? 1 : 0};
+  HIPCHK(launch_init(ia, w.ctrl, pl->dof, st), "init kernels");
+  int it = 0;
+  for (; it < pl->max_iter; ++it) {
+    hipEvent_t* evs = timing ? &pl->ev[5 * it] : nullptr;
+    rc = pl->fp64 ? enqueue_iteration<double>(pl, d_u0, d_U, w, st, evs)
+                  : enqueue_iteration<float>(pl, d_u0, d_U, w, st, evs);
+    if (rc) return rc;
+    // The stop rule cannot fire before the second iteration (it needs a
+    // contraction estimate), so the first check follows iteration 2.
+    if (it >= 1) {
+      HIPCHK(hipMemcpyAsync(pl->h_flag, &w.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+      HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+      if (*pl->h_flag) {
+        ++it;
+        break;
+      }
+    }
+  }
+  Ctrl c;
+  HIPCHK(hipMemcpyAsync(&c, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
+  HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+  const int status = c.done ? c.status : PINT_ENOCONV;
+  if (rep) {
+    std::memset(reinterpret_cast<char*>(rep) + sizeof(size_t), 0, sizeof(pint_report) - sizeof(size_t));
+    rep->status = status;
+    rep->iterations = c.iter;
+    rep->alpha_used = pl->alpha;
+    rep->c_bar = c.c_bar;
+    rep->est_rel_err = c.est;
+    for (int k = 0; k < PINT_HIST && k < c.iter; ++k) {
+      rep->upd_hist[k] = c.upd_hist[k];
+      rep->res_hist[k] = c.res_hist[k];
+    }
+    if (timing) {
+      for (int k = 0; k < c.iter && k < it; ++k)
+        for (int s = 0; s < 4; ++s) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, pl->ev[5 * k + s], pl->ev[5 * k + s + 1]) == hipSuccess)
+            rep->ms_stage[s] += ms;
+        }
+    }
+    rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status != PINT_OK) {
+    set_err(&pl->err, status, status == PINT_ENOCONV ? "not converged within max_iter" : "iteration diverged");
+  }
+  return status;
+}
+
+int pint_residual(pint_plan* pl, const double* d_u0, const double* d_U, double* d_r, void* d_work,
+                  size_t work_bytes, void* stream) {
+  if (!pl || !d_u0 || !d_U || !d_r) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ResidArgs ra = pl->ra;
+  ra.u0 = d_u0;
+  ra.U = d_U;
+  ra.part = w.part;
+  ra.done = nullptr;
+  if (pl->fp64)
+    HIPCHK(launch_resid<double>(pl->dim, pl->n, ra, nullptr, d_r, pl->dtd, pl->nt, 1, st), "residual kernel");
+  else
+    HIPCHK(launch_resid<float>(pl->dim, pl->n, ra, nullptr, d_r, pl->dtf, pl->nt, 1, st), "residual kernel");
+  return PINT_OK;
+}
+
+int pint_dct(pint_plan* pl, const void* d_in, void* d_out, int inverse, void* stream) {
+  if (!pl || !d_in || !d_out) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (pl->fp64)
+    HIPCHK(launch_dct<double>(pl->dim, pl->n, static_cast<const double*>(d_in), static_cast<double*>(d_out), pl->dtd,
+                              pl->nt, inverse != 0, st),
+           "dct kernel");
+  else
+    HIPCHK(launch_dct<float>(pl->dim, pl->n, static_cast<const float*>(d_in), static_cast<float*>(d_out), pl->dtf,
+                             pl->nt, inverse != 0, st),
+           "dct kernel");
+  return PINT_OK;
+}
+
+int pint_time_solve(pint_plan* pl, void* d_S, double c_bar, void* stream) {
+  if (!pl || !d_S) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (pl->fp64) {
+    TimeArgs<double> ta = pl->tad;
+    ta.cbar_val = c_bar;
+    e = launch_time<double>(pl->nt, static_cast<double*>(d_S), ta, st);
+  } else {
+    TimeArgs<float> ta = pl->taf;
+    ta.cbar_val = c_bar;
+    e = launch_time<float>(pl->nt, static_cast<float*>(d_S), ta, st);
+  }
+  if (e != hipSuccess) return hip_fail(pl, e, "time-solve kernel");
+  return PINT_OK;
+}
+
+int pint_precond_apply(pint_plan* pl, const double* d_r, double* d_delta, double c_bar, void* d_work,
+                       size_t work_bytes, void* stream) {
+  if (!pl || !d_r || !d_delta) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)pl->nt * pl->ns;
+  if (pl->fp64) {
+    double* S = static_cast<double*>(w.S);
+    HIPCHK(launch_cast_to<double>(d_r, S, n, st), "cast");
+    HIPCHK(launch_dct<double>(pl->dim, pl->n, S, S, pl->dtd, pl->nt, false, st), "dct");
+  } else {
+    float* S = static_cast<float*>(w.S);
+    HIPCHK(launch_cast_to<float>(d_r, S, n, st), "cast");
+    HIPCHK(launch_dct<float>(pl->dim, pl->n, S, S, pl->dtf, pl->nt, false, st), "dct");
+  }
+  rc = pint_time_solve(pl, w.S, c_bar, stream);
+  if (rc) return rc;
+  UpdArgs ua{nullptr, w.part, nullptr};
+  if (pl->fp64)
+    HIPCHK(launch_update<double>(pl->dim, pl->n, ua, static_cast<double*>(w.S), d_delta, pl->dtd, pl->nt, 1, st),
+           "inverse dct");
+  else
+    HIPCHK(launch_update<float>(pl->dim, pl->n, ua, static_cast<float*>(w.S), d_delta, pl->dtf, pl->nt, 1, st),
+           "inverse dct");
+  return PINT_OK;
+}
+
+int pint_diagnostics(pint_plan* pl, const double* d_U, double* d_mass, double* d_energy, void* stream) {
+  if (!pl || !d_U || !d_mass || !d_energy) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DiagArgs a{d_U, d_mass, d_energy, pl->n, pl->ns, pl->dim, pl->p.eps * pl->p.eps, 1.0 / (pl->h * pl->h),
+             pl->dim == 2 ? pl->h * pl->h : pl->h};
+  HIPCHK(launch_diagnostics(a, pl->nt, st), "diagnostics kernel");
+  return PINT_OK;
+}
+
+}  // extern "C"

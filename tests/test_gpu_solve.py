@@ -1,0 +1,153 @@
+"""End-to-end parity of the all-at-once solve against the sequential oracle
+(GPU), plus the contract and invariant checks.
+
+Bar: relative error max_n ||u_n - u_n^ref||_2 / max_n ||u_n^ref||_2 <= 1e-10
+for the FP64 and the FP32-refined paths (the paper's stopping tolerance,
+Section 5, measured in its L^inf(0,T;L^2) norm).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import allatonce as aao
+from oracle import operators as ops
+from oracle import stepper
+from paper_2304_14021_amd import PintError, Solver
+from workloads import CONFIGS, Problem, initial_datum
+from tests._gpu import dev, host, say, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _run(p, u0, prec, **kw):
+    s = Solver.for_problem(p, precision=prec, device=dev(), **kw)
+    U, rep = s.solve(to_dev(u0), raise_on_error=False)
+    return host(U), rep, s
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c1_biharmonic_1d(prec):
+    say(f"c1 {prec}")
+    p = CONFIGS["c1"]
+    u0 = initial_datum("c1")
+    U, rep, _ = _run(p, u0, prec)
+    ref = stepper.sequential(p, u0)
+    err = stepper.rel_err(U, ref)
+    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
+    assert rep["status"] == 0 and err <= TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_linear_ch_2d_full_size(prec):
+    say(f"c2 {prec}")
+    p = CONFIGS["c2"]
+    u0 = initial_datum("c2")
+    U, rep, _ = _run(p, u0, prec)
+    ref = stepper.sequential(p, u0)
+    err = stepper.rel_err(U, ref)
+    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
+    assert rep["status"] == 0 and err <= TOL
+    assert stepper.rel_err_inf(U, ref) <= 10 * TOL
+
+
+SOLVE_CASES = [
+    Problem(op="biharmonic", dim=1, n=8, nt=4, dt=1e-4, alpha=1e-3),
+    Problem(op="biharmonic", dim=2, n=32, nt=32, dt=1e-5, theta=0.5, alpha=1e-3),
+    Problem(op="linear_ch", dim=1, n=512, nt=1024, dt=1e-7, eps=0.05, beta=0.5, alpha=1e-3),
+    Problem(op="linear_ch", dim=2, n=64, nt=256, dt=1e-5, theta=0.5, eps=0.03, beta=0.4, alpha=1e-3),
+    Problem(op="ch", dim=2, n=64, nt=64, dt=1e-6, eps=0.02, alpha=1e-3),
+    Problem(op="ch", dim=1, n=128, nt=128, dt=1e-5, eps=0.05, alpha=1e-3),
+    Problem(op="ch_eyre", dim=2, n=32, nt=32, dt=1e-5, eps=0.05, alpha=1e-3),
+    Problem(op="linear_ch", dim=2, n=128, nt=1024, dt=1e-6, eps=0.05, beta=0.5, alpha=1e-3),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", SOLVE_CASES, ids=[f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}-th{p.theta}" for p in SOLVE_CASES])
+def test_solve_matches_oracle(p, prec):
+    say(f"solve {prec} {p}")
+    rng = np.random.default_rng(11)
+    amp = 0.3 if p.op in ("ch", "ch_eyre") else 1.0
+    u0 = rng.uniform(-amp, amp, p.slice_shape)
+    U, rep, _ = _run(p, u0, prec)
+    ref = stepper.sequential(p, u0)
+    err = stepper.rel_err(U, ref)
+    say(f"  iterations {rep['iterations']} err {err:.2e}")
+    assert rep["status"] == 0 and err <= TOL
+
+
+def test_ch_invariants_mass_energy():
+    p = Problem(op="ch", dim=2, n=64, nt=64, dt=1e-6, eps=0.01, alpha=1e-3)
+    say(f"ch invariants {p}")
+    rng = np.random.default_rng(12)
+    u0 = rng.uniform(-0.1, 0.1, p.slice_shape)
+    s = Solver.for_problem(p, precision="fp32", device=dev())
+    Ud, rep = s.solve(to_dev(u0))
+    m, e = s.diagnostics(Ud)
+    m, e, U = host(m), host(e), host(Ud)
+    # GPU diagnostics equal the oracle's definitions
+    assert np.allclose(m, [ops.mass(u, p.h) for u in U], rtol=0, atol=1e-14)
+    assert np.allclose(e, [ops.energy(u, p.eps, p.h) for u in U], rtol=1e-12, atol=0)
+    m0 = ops.mass(u0, p.h)
+    assert np.max(np.abs(m - m0)) <= 1e-13 * max(1.0, abs(m0))
+    e_all = np.concatenate([[ops.energy(u0, p.eps, p.h)], e])
+    assert np.all(np.diff(e_all) <= 1e-13 * np.abs(e_all[1:]))
+
+
+def test_constant_state_stays_constant():
+    for op in ("linear_ch", "ch", "ch_eyre"):
+        p = Problem(op=op, dim=2, n=32, nt=16, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)
+        U, rep, _ = _run(p, np.full(p.slice_shape, 0.3), "fp32")
+        assert rep["status"] == 0
+        assert np.max(np.abs(U - 0.3)) < 1e-12
+
+
+def test_deterministic_bitwise():
+    p = CONFIGS["c2"]
+    u0 = initial_datum("c2")
+    s = Solver.for_problem(p, precision="fp32", device=dev())
+    a, _ = s.solve(to_dev(u0))
+    b, _ = s.solve(to_dev(u0))
+    assert torch.equal(a, b)
+
+
+def test_exact_wr_recursion_fp64():
+    # Section 2.2 fully discrete analysis: per cosine mode e_n^k = R^n e_0^k,
+    # e_0^k = -alpha e_{N_t}^{k-1} / (1 - alpha R^{N_t}), for every iterate.
+    p = Problem(op="biharmonic", dim=1, n=16, nt=8, dt=2e-4, alpha=0.2)
+    rng = np.random.default_rng(13)
+    u0 = rng.uniform(-1, 1, 16)
+    U0 = rng.uniform(-1, 1, p.shape)
+    S = stepper.sequential(p, u0)
+    lam = 2.0 * 256 * (np.cos(np.arange(16) * np.pi / 16) - 1.0)
+    R = 1.0 / (1.0 + p.dt * lam ** 2)
+    prev = aao.dct2(U0 - S, 1)[-1]
+    for k in range(1, 4):
+        s = Solver.for_problem(p, precision="fp64", device=dev(), max_iter=k, broadcast_u0=False)
+        U, rep = s.solve(to_dev(u0), to_dev(U0), raise_on_error=False)
+        e = aao.dct2(host(U) - S, 1)
+        e0 = -p.alpha * prev / (1 - p.alpha * R ** p.nt)
+        expect = R[None, :] ** np.arange(1, p.nt + 1)[:, None] * e0[None, :]
+        assert rep["iterations"] == k
+        assert np.max(np.abs(e - expect)) <= 1e-9 * np.max(np.abs(e)) + 1e-15
+        prev = e[-1]
+
+
+def test_enoconv_partial_report():
+    p = CONFIGS["c2"]
+    s = Solver.for_problem(p, precision="fp32", device=dev(), max_iter=1)
+    U, rep = s.solve(to_dev(initial_datum("c2")), raise_on_error=False)
+    assert rep["status"] == -2 and rep["iterations"] == 1
+    assert np.all(np.isfinite(host(U)))
+    with pytest.raises(PintError) as ei:
+        s.solve(to_dev(initial_datum("c2")))
+    assert ei.value.code == -2
+
+
+def test_nan_input_diverged():
+    p = Problem(op="linear_ch", dim=2, n=32, nt=16, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)
+    u0 = np.zeros(p.slice_shape)
+    u0[3, 4] = np.nan
+    U, rep, _ = _run(p, u0, "fp32")
+    assert rep["status"] == -3
