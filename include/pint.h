@@ -72,6 +72,11 @@ extern "C" {
 #define PINT_PREC_FP32_NOREFINE 2  /* residual and update in FP32 too          */
 #define PINT_PREC_BF16_REFINE   3  /* dense time contraction with BF16 operands,
                                       FP32 accumulate; residual+update FP64    */
+#define PINT_PREC_MIXED         4  /* forward spatial DCT in FP64 (its rounding
+                                      would be amplified by the stiffness ratio
+                                      of the shifted spatial solves), time solve
+                                      and inverse DCT in FP32; residual+update
+                                      FP64                                     */
 
 /* ------------------------------------------------------------- time path */
 #define PINT_TIME_AUTO  0          /* FFT over time (alpha-circulant)          */
@@ -115,8 +120,10 @@ typedef struct pint_report {
   double est_rel_err;          /* error estimate rho/(1-rho) * |dU|/|U|          */
   double res_hist[PINT_HIST];  /* max_n ||r_n||_2 of the iterate entering step k */
   double upd_hist[PINT_HIST];  /* max_n ||delta_n||_2 / max_n ||u_n||_2, step k */
-  double ms_stage[8];          /* residual+DCT, time solve, IDCT+update, control,
-                                  (FLAG_STAGE_TIMING only), then unused        */
+  double ms_stage[8];          /* summed over iterations (FLAG_STAGE_TIMING only):
+                                  [0] residual + x-DCT-II, [1] y-DCT-II,
+                                  [2] time solve, [3] y-DCT-III,
+                                  [4] x-DCT-III + update, [5] control; rest 0  */
   double ms_total;             /* wall time of the solve call (host clock)      */
 } pint_report;
 
@@ -171,7 +178,9 @@ int pint_solve(pint_plan* plan, const double* d_u0, double* d_U, void* d_work, s
                void* stream, pint_report* rep);
 
 /* ---- stage entry points (same kernels as pint_solve; used for per-stage parity) ----
- * Working precision W: double for PINT_PREC_FP64, float otherwise.  d_work must
+ * Working precision W: double for PINT_PREC_FP64, float otherwise (for
+ * PINT_PREC_MIXED the forward transform inside pint_solve and
+ * pint_precond_apply is FP64, the stage DCT and time solve are FP32).  d_work must
  * be a workspace as for pint_solve.  All are asynchronous on `stream`.
  */
 

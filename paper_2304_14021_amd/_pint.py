@@ -19,7 +19,7 @@ PINT_ECANCELED = -7
 PINT_ENOTFOUND = -8
 
 OPS = {"biharmonic": 0, "linear_ch": 1, "ch": 2, "ch_eyre": 3}
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3, "mixed": 4}
 TIME_PATHS = {"auto": 0, "fft": 1, "dense": 2}
 FLAG_INIT_BROADCAST_U0 = 0x1
 FLAG_STAGE_TIMING = 0x2
@@ -199,6 +199,6 @@ def report_dict(rep: Report) -> dict:
         "est_rel_err": rep.est_rel_err,
         "res_hist": list(rep.res_hist[:k]),
         "upd_hist": list(rep.upd_hist[:k]),
-        "ms_stage": list(rep.ms_stage[:4]),
+        "ms_stage": list(rep.ms_stage[:6]),
         "ms_total": rep.ms_total,
     }

@@ -1,223 +1,356 @@
 // HIP kernels (gfx950) of the all-at-once space-time solve, FFT path.
 //
-// One outer iteration (correction form U <- U + P_alpha^{-1} r(U)) is
-//   k_resid_dct   a1 + a2: FP64 residual of one time level (or a pair of 1D
-//                 levels), rounded to the working type W, then its orthonormal
-//                 DCT-II in LDS  ->  S[n][k]  (W)
-//   k_time_solve  a3-a5: per tile of spatial cosine modes, Gamma_alpha scaling,
-//                 FFT over time, shifted complex divide, inverse FFT,
-//                 Gamma_alpha^{-1} scaling, in place on S (Section 2.1,
-//                 eq. pintiter1; Section 4.1, eq. pintiter_CH)
-//   k_idct_update a6: DCT-III of one level in LDS, U_n += delta_n in FP64,
-//                 per-level partial norms
-//   k_finalize    a7: fixed-order reduction of the partials, scalar averaged
-//                 Jacobian, stop rule and divergence guard (one workgroup)
-// All kernels return at once when the device stop flag is set, so several
-// iterations may be enqueued ahead of the host's check.
+// Data: U [N_t][N_y][N_x] FP64 (caller's), S [N_t][k_y][k_x] in the working
+// type W (float or double, the spectral scratch).  One outer iteration,
+// correction form U <- U + P_alpha^{-1} r(U), is
+//   k_rows_fwd   a1 + a2 (x): FP64 residual of a block of RB rows (with a
+//                two-row halo for the 13-point stencil), then the orthonormal
+//                DCT-II along x of those rows  ->  S
+//   k_cols<fwd>  a2 (y): DCT-II along y of a tile of XB columns of one level
+//   k_time_solve a3-a5: per tile of M spatial cosine modes, Gamma_alpha scaling,
+//                FFT over time, shifted complex divide, inverse FFT,
+//                Gamma_alpha^{-1} scaling (Section 2.1, eq. pintiter1;
+//                Section 4.1, eqs. pintiter_CH and pintiter_CH_eyre)
+//   k_cols<inv>  a6 (y): DCT-III along y
+//   k_rows_inv   a6 (x): DCT-III along x, U += delta in FP64, partial norms
+//   k_finalize   a7: fixed-order reduction, scalar averaged Jacobian, stop rule
+// In 1D the "rows" are time levels and the column passes are skipped.  Every
+// transform pass moves data global -> LDS (reordered and packed two real
+// sequences per complex one) -> radix-8 Stockham FFT in LDS -> global, so each
+// pass reads and writes its tile once.  All kernels return at once when the
+// device stop flag is set, so iterations can be enqueued ahead of the host's
+// check.
 #include "pint.h"
 #include "pint_kernels.hpp"
 #include "fft_lds.hpp"
 
-namespace pint {
+#include <type_traits>
 
-// ------------------------------------------------------------------ sizing
-// Threads per workgroup of the per-slice kernels (2D: one N x N level).
-constexpr int slice_threads(int n) { return n >= 128 ? 1024 : (n >= 32 ? 256 : 64); }
-// LDS bytes of the per-slice kernels: the FP64 stencil array (N^2 doubles)
-// and the DCT array (N^2 + 2N reals of W) share one buffer.
-template <typename T, int N, int ROWS>
-struct slice_lds {
-  static constexpr int a = 8 * N * ROWS;
-  static constexpr int b = int(sizeof(T)) * dct_lds_reals<N, ROWS>::value;
-  static constexpr int red = 8 * 4 * 1024;
-  static constexpr int value0 = a > b ? a : b;
-  static constexpr int value = value0 > red ? value0 : red;
-};
+namespace pint {
 
 // Neumann (ghost-reflection) index clamp.
 __device__ __forceinline__ int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
-// ---------------------------------------------------------------- residual
-// DIM == 2: ROWS == N rows of one level n = blockIdx.x.
-// DIM == 1: ROWS levels n0 .. n0+ROWS-1 (n0 = blockIdx.x * ROWS), one row each.
-// The residual of level n is r_n = -(u_n - u_{n-1})/dt + Lap_h g_n with
-//   g = c3 v^3 + c1 v + c1p u_{n-1} + c2 Lap_h v,  v = theta u_n + (1-theta) u_{n-1}
-// which covers
-//   linear theta-method: c3 = 0, c1 = -beta^2, c1p = 0, c2 = -eps^2
-//   CH fully implicit  : theta = 1, c3 = 1, c1 = -1, c1p = 0, c2 = -eps^2
-//   CH Eyre splitting  : theta = 1, c3 = 1, c1 = 0, c1p = -1, c2 = -eps^2
-// (the alpha = 0 rows of eqs. all-at-once1, nonlinear_G and nonlinear_Q).
-// MODE 0: write the DCT-II of r (type T) to S.  MODE 1: write r in FP64 to rout.
-template <typename T, int DIM, int N, int ROWS, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_resid_dct(ResidArgs a, T* __restrict__ S, double* __restrict__ rout,
-                                                   DctTables<T> dt) {
+template <typename T>
+__device__ __forceinline__ T& comp(cx<T>& c, int i) {
+  return i ? c.y : c.x;
+}
+
+// Copy a small read-only table into LDS (caller synchronizes before use).
+template <typename T, int NT, int LEN>
+__device__ __forceinline__ void table_to_lds(cx<T>* dst, const cx<T>* __restrict__ src) {
+#pragma unroll
+  for (int i = 0; i < cdiv_i(LEN, NT); ++i) {
+    const int j = threadIdx.x + i * NT;
+    if (LEN % NT == 0 || j < LEN) dst[j] = src[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1 + a2(x).  DIM == 2: block b covers rows y0 .. y0+RB-1 of level
+// n = b / (N/RB).  DIM == 1: block b covers levels b*RB .. b*RB+RB-1 (one
+// row each).  The residual of level n is
+//   r_n = -(u_n - u_{n-1})/dt + Lap_h g_n,
+//   g   = c3 v^3 + c1 v + c1p u_{n-1} + c2 Lap_h v,  v = theta u_n + (1-theta) u_{n-1},
+// which is the alpha = 0 row of eq. all-at-once1 (c3 = 0, c1 = -beta^2,
+// c1p = 0, c2 = -eps^2; biharmonic c1 = 0, c2 = -1), of eq. nonlinear_G
+// (theta = 1, c3 = 1, c1 = -1, c2 = -eps^2) and of eq. nonlinear_Q
+// (theta = 1, c3 = 1, c1 = 0, c1p = -1, c2 = -eps^2).  Lap_h is the
+// cell-centred Neumann Laplacian: neighbours outside the grid are reflected.
+// With a.bcast the iterate is u0 at every level (first iteration from the
+// broadcast initial guess), so u_n - u_{n-1} = 0.
+// MODE 0 writes the x-DCT of r (type T) to S; MODE 1 writes r (FP64) to rout.
+template <int DIM, int N, int RB>
+struct rows_geom {
+  static constexpr int NBL = DIM == 2 ? N / RB : 1;  // blocks per level
+  static constexpr int H = DIM == 2 ? 2 : 0;         // v halo rows
+  static constexpr int VR = RB + 2 * H;              // v rows in LDS (positions y0-2 .. y0+RB+1)
+  static constexpr int GR = RB + (DIM == 2 ? 2 : 0); // g rows (positions y0-1 .. y0+RB)
+  static constexpr int P = RB / 2;                   // packed complex sequences
+  static constexpr int ES = P + 1;                   // odd stride of the complex scratch
+};
+
+template <typename T, typename TO, int DIM, int N, int RB, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S, double* __restrict__ rout,
+                                                  DctTables<T> dt) {
   if (a.done && *a.done) return;
-  constexpr int NPT = N * ROWS / NT;
-  static_assert(NPT * NT == N * ROWS, "threads must divide the slab");
-  __shared__ __align__(16) unsigned char lds[slice_lds<T, N, ROWS>::value];
+  using Gm = rows_geom<DIM, N, RB>;
+  constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
+  constexpr int VB = VR * N * 8, GB = GR * N * 8, ZB = N * ES * int(sizeof(cx<T>));
+  constexpr int R0 = VB > ZB ? VB : ZB;
+  constexpr int NV = DIM == 2 ? 1 : RB;
+  constexpr int RED = NT * NV * 8;  // reduction scratch, reuses the G region
+  __shared__ __align__(16) unsigned char lds[R0 + (GB > RED ? GB : RED)];
+  __shared__ cx<T> s_tw[N], s_wq[N];
   double* V = reinterpret_cast<double*>(lds);
-  T* A = reinterpret_cast<T*>(lds);
+  cx<T>* z = reinterpret_cast<cx<T>*>(lds);
+  double* G = reinterpret_cast<double*>(lds + R0);
+  if (MODE == 0) {
+    table_to_lds<T, NT, N>(s_tw, dt.tw);
+    table_to_lds<T, NT, N>(s_wq, dt.wq);
+  }
   const int tid = threadIdx.x;
-  const int ns = (DIM == 2) ? N * N : N;
+  const int b = blockIdx.x;
+  const int lev = DIM == 2 ? b / NBL : b * RB;
+  const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
+  const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
+  const bool bc = a.bcast != 0;
   const double th = a.theta, omth = 1.0 - a.theta;
 
-  double d[NPT];
-  // Phase 1: v = theta u_n + (1-theta) u_{n-1} -> LDS; d = u_n - u_{n-1} kept.
+  // Phase 1: v at positions y0-2 .. y0+RB+1 (clamped rows) -> V.  The own
+  // rows' time differences d = u_n - u_{n-1} stay in registers for phase 3
+  // (same point-to-thread map).  All loads are issued before any is used.
+  constexpr int HW = 2 * Gm::H * N, OW = RB * N;
+  constexpr int ITH = cdiv_i(HW, NT), ITO = cdiv_i(OW, NT);
+  double d[ITO];
+  {
+    double hn[ITH > 0 ? ITH : 1], hm[ITH > 0 ? ITH : 1], on[ITO], om[ITO];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;                      // [row][x] within the slab
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + row;
-    const int off = (DIM == 2) ? idx : x;
-    const double un = a.U[(size_t)n * ns + off];
-    const double um = (n == 0) ? a.u0[off] : a.U[(size_t)(n - 1) * ns + off];
-    d[i] = un - um;
-    V[idx] = th * un + omth * um;
+    for (int i = 0; i < ITH; ++i) {
+      const int w = tid + i * NT;
+      hn[i] = hm[i] = 0.0;
+      if (HW % NT == 0 || w < HW) {
+        const int hr = w / N, x = w - (w / N) * N;
+        const int vr = hr < Gm::H ? hr : hr + RB;
+        const int off = clampi(y0 - Gm::H + vr, N) * N + x;
+        if (bc) {
+          hn[i] = hm[i] = a.u0[off];
+        } else {
+          hn[i] = a.U[lev * ns + off];
+          hm[i] = lev == 0 ? a.u0[off] : a.U[(lev - 1) * ns + off];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITO; ++i) {
+      const int w = tid + i * NT;
+      on[i] = om[i] = 0.0;
+      if (OW % NT == 0 || w < OW) {
+        const int rr = w / N, x = w - (w / N) * N;
+        const int n = DIM == 2 ? lev : lev + rr;
+        const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+        if (bc) {
+          on[i] = om[i] = a.u0[off];
+        } else {
+          on[i] = a.U[n * ns + off];
+          om[i] = n == 0 ? a.u0[off] : a.U[(n - 1) * ns + off];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITH; ++i) {
+      const int w = tid + i * NT;
+      if (HW % NT == 0 || w < HW) {
+        const int hr = w / N, x = w - (w / N) * N;
+        const int vr = hr < Gm::H ? hr : hr + RB;
+        V[vr * N + x] = th * hn[i] + omth * hm[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITO; ++i) {
+      const int w = tid + i * NT;
+      d[i] = on[i] - om[i];
+      if (OW % NT == 0 || w < OW) V[Gm::H * N + w] = th * on[i] + omth * om[i];
+    }
   }
   __syncthreads();
-  // Phase 2: g (needs Lap_h v from LDS).
-  double g[NPT];
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const double v = V[idx];
-    double lap = V[row * N + clampi(x - 1, N)] + V[row * N + clampi(x + 1, N)] - 2.0 * v;
-    if (DIM == 2) lap += V[clampi(row - 1, N) * N + x] + V[clampi(row + 1, N) * N + x] - 2.0 * v;
-    lap *= a.inv_h2;
-    const double um = v - th * d[i];
-    g[i] = a.c3 * v * v * v + a.c1 * v + a.c1p * um + a.c2 * lap;
+  // Phase 2: g at positions clamp(y0-1 .. y0+RB) -> G.
+  for (int idx = tid; idx < GR * N; idx += NT) {
+    const int gr = idx / N, x = idx - (idx / N) * N;
+    int c, yg = 0;
+    if (DIM == 2) {
+      yg = clampi(y0 - 1 + gr, N);
+      c = yg - (y0 - 2);  // V row holding position yg
+    } else {
+      c = gr;
+    }
+    const double v = V[c * N + x];
+    double lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - 2.0 * v;
+    if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - 2.0 * v;
+    double g = a.c3 * v * v * v + a.c1 * v + a.c2 * (lap * a.inv_h2);
+    if (a.c1p != 0.0) {
+      const int n = DIM == 2 ? lev : lev + gr;
+      const int off = DIM == 2 ? yg * N + x : x;
+      const double um = (bc || n == 0) ? a.u0[off] : a.U[(n - 1) * ns + off];
+      g += a.c1p * um;
+    }
+    G[idx] = g;
   }
   __syncthreads();
+  // Phase 3: r on the own rows; packed into z (overlays V, which is dead).
+  double rsq[NV];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) V[tid + i * NT] = g[i];
-  __syncthreads();
-  // Phase 3: r = -d/dt + Lap_h g.
-  double rsq[DIM == 2 ? 1 : ROWS];
+  for (int q = 0; q < NV; ++q) rsq[q] = 0.0;
 #pragma unroll
-  for (int q = 0; q < (DIM == 2 ? 1 : ROWS); ++q) rsq[q] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const double gc = V[idx];
-    double lap = V[row * N + clampi(x - 1, N)] + V[row * N + clampi(x + 1, N)] - 2.0 * gc;
-    if (DIM == 2) lap += V[clampi(row - 1, N) * N + x] + V[clampi(row + 1, N) * N + x] - 2.0 * gc;
+  for (int i = 0; i < ITO; ++i) {
+    const int w = tid + i * NT;
+    if (!(OW % NT == 0 || w < OW)) continue;
+    const int rr = w / N, x = w - (w / N) * N;
+    const int gc = DIM == 2 ? rr + 1 : rr;
+    const double gv = G[gc * N + x];
+    double lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - 2.0 * gv;
+    if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - 2.0 * gv;
     const double r = -d[i] * a.inv_dt + lap * a.inv_h2;
-    g[i] = r;
-    if (DIM == 2) rsq[0] += r * r;
-    else {
 #pragma unroll
-      for (int q = 0; q < (DIM == 2 ? 1 : ROWS); ++q) rsq[q] += (row == q) ? r * r : 0.0;
+    for (int qq = 0; qq < NV; ++qq)
+      if (DIM == 2 || qq == rr) rsq[qq] += r * r;
+    if (MODE == 1) {
+      const int n = DIM == 2 ? lev : lev + rr;
+      const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+      rout[n * ns + off] = r;
+    } else {
+      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(r);
     }
   }
   __syncthreads();
-  if (MODE == 1) {
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int idx = tid + i * NT;
-      const int row = idx / N, x = idx - (idx / N) * N;
-      const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + row;
-      const int off = (DIM == 2) ? idx : x;
-      rout[(size_t)n * ns + off] = g[i];
+  if (MODE == 0) {
+    fft_lds<T, N, P, ES, NT, -1>(z, s_tw);
+    constexpr int K = N / 2 + 1;
+    for (int w = tid; w < K * P; w += NT) {
+      const int p = w / K, k = w - (w / K) * K;
+      T x1k, x2k, x1n, x2n;
+      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
+                 x1n, x2n);
+      const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
+      const size_t r1 = r0 + N;
+      S[r0 + k] = TO(x1k);
+      S[r1 + k] = TO(x2k);
+      if (k > 0 && k < N / 2) {
+        S[r0 + N - k] = TO(x1n);
+        S[r1 + N - k] = TO(x2n);
+      }
     }
-    return;
   }
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) A[tid + i * NT] = T(g[i]);
-  __syncthreads();
-  dct2_rows<T, N, ROWS, N, NT>(A, dt.tw, dt.wq);
-  if (DIM == 2) dct2_cols<T, N, N, NT>(A, dt.tw, dt.wq);
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + row;
-    const int off = (DIM == 2) ? idx : x;
-    S[(size_t)n * ns + off] = A[idx];
-  }
-  __syncthreads();
-  // Per-level partial sum of r^2.
-  constexpr int NV = (DIM == 2) ? 1 : ROWS;
+  // Partial sums of r^2 (G is free scratch now).
   bool ismax[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) ismax[q] = false;
-  block_reduce<NT, NV>(reinterpret_cast<double*>(lds), rsq, ismax);
+  block_reduce<NT, NV>(G, rsq, ismax);
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + q;
-      a.part[(size_t)n * PART_STRIDE + PART_RSQ] = rsq[q];
+      const int slot = DIM == 2 ? b : lev + q;  // [level][block] (NBL = 1 in 1D)
+      a.part[size_t(slot) * PART_STRIDE + PART_RSQ] = rsq[q];
     }
   }
 }
 
-// ------------------------------------------------------- inverse + update
-// delta = DCT-III of S level(s); U += delta (FP64); partial sums of
-// delta^2, U^2, 3U^2 and max|delta| per level.  MODE 1 writes delta in FP64
-// to dout instead of updating U.
-template <typename T, int DIM, int N, int ROWS, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_idct_update(UpdArgs a, const T* __restrict__ S, double* __restrict__ dout,
-                                                     DctTables<T> dt) {
+// ---------------------------------------------------------------------------
+// a6 (x) + update.  Same blocks as k_rows_fwd.  delta = DCT-III along x of
+// the RB rows of S; U += delta in FP64 (with a.bcast: U = u0 + delta); partial
+// sums of delta^2, U^2, 3U^2 and max|delta| per [level][block].  MODE 1 writes
+// delta (FP64) to dout instead of updating U.
+template <typename T, int DIM, int N, int RB, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict__ S, double* __restrict__ dout,
+                                                  DctTables<T> dt) {
   if (a.done && *a.done) return;
-  constexpr int NPT = N * ROWS / NT;
-  static_assert(NPT * NT == N * ROWS, "threads must divide the slab");
-  __shared__ __align__(16) unsigned char lds[slice_lds<T, N, ROWS>::value];
-  T* A = reinterpret_cast<T*>(lds);
+  using Gm = rows_geom<DIM, N, RB>;
+  constexpr int P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
+  constexpr int NV = DIM == 2 ? 1 : RB;
+  __shared__ __align__(16) cx<T> z[N * ES];
+  __shared__ double red[NT * 4 * NV];
+  __shared__ cx<T> s_tw[N], s_wi[N];
+  table_to_lds<T, NT, N>(s_tw, dt.tw);
+  table_to_lds<T, NT, N>(s_wi, dt.wi);
   const int tid = threadIdx.x;
-  const int ns = (DIM == 2) ? N * N : N;
+  const int b = blockIdx.x;
+  const int lev = DIM == 2 ? b / NBL : b * RB;
+  const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
+  const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
+  constexpr int K = N / 2 + 1;
+  {
+    constexpr int W = K * P, IT = cdiv_i(W, NT);
+    T x1k[IT], x2k[IT], x1n[IT], x2n[IT];
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + row;
-    const int off = (DIM == 2) ? idx : x;
-    A[idx] = S[(size_t)n * ns + off];
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      x1k[i] = x2k[i] = x1n[i] = x2n[i] = T(0);
+      if (w < W) {
+        const int p = w / K, k = w - (w / K) * K;
+        const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
+        const size_t r1 = r0 + N;
+        x1k[i] = S[r0 + k];
+        x2k[i] = S[r1 + k];
+        if (k) {
+          x1n[i] = S[r0 + N - k];
+          x2n[i] = S[r1 + N - k];
+        }
+      }
+    }
+    __syncthreads();  // s_tw / s_wi complete
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < W) {
+        const int p = w / K, k = w - (w / K) * K;
+        cx<T> zk, zn;
+        dct3_join(x1k[i], x2k[i], x1n[i], x2n[i], s_wi[k], zk, zn);
+        z[k * ES + p] = zk;
+        if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
+      }
+    }
   }
   __syncthreads();
-  if (DIM == 2) dct3_cols<T, N, N, NT>(A, dt.tw, dt.wi);
-  dct3_rows<T, N, ROWS, N, NT>(A, dt.tw, dt.wi);
-  constexpr int NV1 = (DIM == 2) ? 1 : ROWS;
-  double acc[4 * NV1];
+  fft_lds<T, N, P, ES, NT, +1>(z, s_tw);
+  double acc[4 * NV];
 #pragma unroll
-  for (int q = 0; q < 4 * NV1; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 4 * NV; ++q) acc[q] = 0.0;
+  const T inv_n = T(1) / T(N);
+  {
+    constexpr int W = RB * N, IT = cdiv_i(W, NT);
+    constexpr int BATCH = IT < 8 ? IT : 8;
 #pragma unroll
-  for (int i = 0; i < NPT; ++i) {
-    const int idx = tid + i * NT;
-    const int row = idx / N, x = idx - (idx / N) * N;
-    const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + row;
-    const int off = (DIM == 2) ? idx : x;
-    const double del = double(A[idx]);
-    const int q = (DIM == 2) ? 0 : row;
-    if (MODE == 1) {
-      dout[(size_t)n * ns + off] = del;
-      continue;
-    }
-    const size_t gi = (size_t)n * ns + off;
-    const double u = a.U[gi] + del;
-    a.U[gi] = u;
+    for (int i0 = 0; i0 < IT; i0 += BATCH) {
+      double uo[BATCH];
 #pragma unroll
-    for (int qq = 0; qq < NV1; ++qq) {
-      if (qq == q) {
-        acc[4 * qq + 0] += del * del;
-        acc[4 * qq + 1] += u * u;
-        acc[4 * qq + 2] += 3.0 * u * u;
-        const double ad = del < 0 ? -del : del;
-        acc[4 * qq + 3] = (ad != ad || ad > acc[4 * qq + 3]) ? ad : acc[4 * qq + 3];
+      for (int q = 0; q < BATCH; ++q) {
+        const int idx = tid + (i0 + q) * NT;
+        uo[q] = 0.0;
+        if (MODE == 0 && i0 + q < IT && (W % NT == 0 || idx < W)) {
+          const int rr = idx / N, x = idx - (idx / N) * N;
+          const int n = DIM == 2 ? lev : lev + rr;
+          const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+          uo[q] = a.bcast ? a.u0[off] : a.U[n * ns + off];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q) {
+        const int idx = tid + (i0 + q) * NT;
+        if (!(i0 + q < IT && (W % NT == 0 || idx < W))) continue;
+        const int rr = idx / N, x = idx - (idx / N) * N;
+        const double del = double(comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n);
+        const int n = DIM == 2 ? lev : lev + rr;
+        const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+        const size_t gi = n * ns + off;
+        if (MODE == 1) {
+          dout[gi] = del;
+          continue;
+        }
+        const double u = uo[q] + del;
+        a.U[gi] = u;
+#pragma unroll
+        for (int qq = 0; qq < NV; ++qq) {
+          if (DIM == 2 || qq == rr) {
+            acc[4 * qq + 0] += del * del;
+            acc[4 * qq + 1] += u * u;
+            acc[4 * qq + 2] += 3.0 * u * u;
+            const double ad = del < 0 ? -del : del;
+            acc[4 * qq + 3] = (ad != ad || ad > acc[4 * qq + 3]) ? ad : acc[4 * qq + 3];
+          }
+        }
       }
     }
   }
   if (MODE == 1) return;
-  __syncthreads();
-  bool ismax[4 * NV1];
+  bool ismax[4 * NV];
 #pragma unroll
-  for (int q = 0; q < 4 * NV1; ++q) ismax[q] = (q % 4) == 3;
-  block_reduce<NT, 4 * NV1>(reinterpret_cast<double*>(lds), acc, ismax);
+  for (int q = 0; q < 4 * NV; ++q) ismax[q] = (q % 4) == 3;
+  block_reduce<NT, 4 * NV>(red, acc, ismax);
   if (tid == 0) {
 #pragma unroll
-    for (int q = 0; q < NV1; ++q) {
-      const int n = (DIM == 2) ? blockIdx.x : blockIdx.x * ROWS + q;
-      double* pp = a.part + (size_t)n * PART_STRIDE;
+    for (int q = 0; q < NV; ++q) {
+      const int slot = DIM == 2 ? b : lev + q;
+      double* pp = a.part + size_t(slot) * PART_STRIDE;
       pp[PART_DSQ] = acc[4 * q + 0];
       pp[PART_USQ] = acc[4 * q + 1];
       pp[PART_U2] = acc[4 * q + 2];
@@ -226,43 +359,203 @@ __global__ __launch_bounds__(NT) void k_idct_update(UpdArgs a, const T* __restri
   }
 }
 
-// ------------------------------------------------------------- time solve
-// One workgroup per tile of M consecutive spatial modes k (M even): the M
-// real sequences over time are packed into M/2 complex ones, transformed
-// together, split into their Hermitian halves, divided by
+// ---------------------------------------------------------------------------
+// a2 (y) forward / a6 (y) inverse: orthonormal DCT-II / DCT-III along y of a
+// tile of XB columns of one level, from Sin (type T) to Sout (type TO; the
+// same array when TO == T: the tile is read completely before it is written).  Columns 2c and 2c+1 are
+// packed into one complex sequence; consecutive threads take consecutive c.
+template <typename T, typename TO, int N, int XB, int NT, bool INV>
+__global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* __restrict__ done,
+                                              DctTables<T> dt) {
+  if (done && *done) return;
+  constexpr int C = XB / 2, ES = C, NBX = N / XB, K = N / 2 + 1;
+  __shared__ __align__(16) cx<T> z[N * ES];
+  __shared__ cx<T> s_tw[N], s_w[N];
+  table_to_lds<T, NT, N>(s_tw, dt.tw);
+  table_to_lds<T, NT, N>(s_w, INV ? dt.wi : dt.wq);
+  const int tid = threadIdx.x;
+  const int lev = blockIdx.x / NBX;
+  const int x0 = (blockIdx.x - lev * NBX) * XB;
+  const T* base = Sin + size_t(lev) * N * N + x0;
+  TO* obase = Sout + size_t(lev) * N * N + x0;
+  if (!INV) {
+    constexpr int W = N * C, IT = cdiv_i(W, NT);
+    cx<T> x[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (W % NT == 0 || w < W) {
+        const int m = w / C, c = w - (w / C) * C;
+        x[i] = *reinterpret_cast<const cx<T>*>(base + size_t(dct_perm<N>(m)) * N + 2 * c);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (W % NT == 0 || w < W) z[(w / C) * ES + (w - (w / C) * C)] = x[i];
+    }
+    __syncthreads();
+    fft_lds<T, N, C, ES, NT, -1>(z, s_tw);
+    for (int w = tid; w < K * C; w += NT) {
+      const int k = w / C, c = w - (w / C) * C;
+      T x1k, x2k, x1n, x2n;
+      dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
+                 x1n, x2n);
+      *reinterpret_cast<cx<TO>*>(obase + size_t(k) * N + 2 * c) = mk(TO(x1k), TO(x2k));
+      if (k > 0 && k < N / 2)
+        *reinterpret_cast<cx<TO>*>(obase + size_t(N - k) * N + 2 * c) = mk(TO(x1n), TO(x2n));
+    }
+  } else {
+    constexpr int W = K * C, IT = cdiv_i(W, NT);
+    cx<T> xk[IT], xn[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      xk[i] = xn[i] = mk(T(0), T(0));
+      if (w < W) {
+        const int k = w / C, c = w - (w / C) * C;
+        xk[i] = *reinterpret_cast<const cx<T>*>(base + size_t(k) * N + 2 * c);
+        if (k) xn[i] = *reinterpret_cast<const cx<T>*>(base + size_t(N - k) * N + 2 * c);
+      }
+    }
+    __syncthreads();  // s_tw / s_w complete
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (w < W) {
+        const int k = w / C, c = w - (w / C) * C;
+        cx<T> zk, zn;
+        dct3_join(xk[i].x, xk[i].y, xn[i].x, xn[i].y, s_w[k], zk, zn);
+        z[k * ES + c] = zk;
+        if (k > 0 && k < N / 2) z[(N - k) * ES + c] = zn;
+      }
+    }
+    __syncthreads();
+    fft_lds<T, N, C, ES, NT, +1>(z, s_tw);
+    const T inv_n = T(1) / T(N);
+    for (int w = tid; w < N * C; w += NT) {
+      const int m = w / C, c = w - (w / C) * C;
+      const cx<T> v = scale(z[m * ES + c], inv_n);
+      *reinterpret_cast<cx<TO>*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) = mk(TO(v.x), TO(v.y));
+    }
+  }
+}
+
+// Stand-alone x-DCT of RB rows (stage entry point): plain copy in, DCT, out.
+template <typename T, int DIM, int N, int RB, int NT, bool INV>
+__global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __restrict__ out, DctTables<T> dt) {
+  using Gm = rows_geom<DIM, N, RB>;
+  constexpr int P = Gm::P, ES = Gm::ES, K = N / 2 + 1;
+  __shared__ __align__(16) cx<T> z[N * ES];
+  const int tid = threadIdx.x;
+  const size_t row0 = size_t(blockIdx.x) * RB;  // rows are contiguous in both 1D and 2D layouts
+  if (!INV) {
+    for (int idx = tid; idx < RB * N; idx += NT) {
+      const int rr = idx / N, x = idx - (idx / N) * N;
+      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = in[(row0 + rr) * N + x];
+    }
+    __syncthreads();
+    fft_lds<T, N, P, ES, NT, -1>(z, dt.tw);
+    for (int w = tid; w < K * P; w += NT) {
+      const int p = w / K, k = w - (w / K) * K;
+      T x1k, x2k, x1n, x2n;
+      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], dt.wq[k], dt.wq[(N - k) & (N - 1)], x1k, x2k,
+                 x1n, x2n);
+      const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
+      out[r0 + k] = x1k;
+      out[r1 + k] = x2k;
+      if (k > 0 && k < N / 2) {
+        out[r0 + N - k] = x1n;
+        out[r1 + N - k] = x2n;
+      }
+    }
+  } else {
+    for (int w = tid; w < K * P; w += NT) {
+      const int p = w / K, k = w - (w / K) * K;
+      const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
+      cx<T> zk, zn;
+      dct3_join(in[r0 + k], in[r1 + k], k ? in[r0 + N - k] : T(0), k ? in[r1 + N - k] : T(0), dt.wi[k], zk, zn);
+      z[k * ES + p] = zk;
+      if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
+    }
+    __syncthreads();
+    fft_lds<T, N, P, ES, NT, +1>(z, dt.tw);
+    const T inv_n = T(1) / T(N);
+    for (int idx = tid; idx < RB * N; idx += NT) {
+      const int rr = idx / N, x = idx - (idx / N) * N;
+      out[(row0 + rr) * N + x] = comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3-a5.  One workgroup per tile of M consecutive spatial modes k (M even):
+// the M real sequences over time are scaled by a^j, packed into M/2 complex
+// ones, transformed together, split into their Hermitian halves, divided by
 //   sigma_{l,k} = lambda1_l + p_l lam_k + q_l lam_k^2,   l = 0..N_t/2,
-// (p_l = pco_l - c_bar for the CH operators), re-packed and transformed back.
+// (p_l = pco_l - c_bar for the CH operators), re-packed, transformed back and
+// scaled by a^{-j}/N_t.
 template <typename T, int NTT, int M, int NT>
 __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
   constexpr int C = M / 2;
   __shared__ __align__(16) cx<T> z[NTT * C];
+  __shared__ cx<T> s_tw[NTT];
+  table_to_lds<T, NT, NTT>(s_tw, ta.tw);
   const int tid = threadIdx.x;
   const int col0 = blockIdx.x * M;
-  const int ns = ta.ns;
-  constexpr int W = NTT * C;
-  for (int w = tid; w < W; w += NT) {
-    const int j = w / C, c = w - (w / C) * C;
-    const cx<T> x = *reinterpret_cast<const cx<T>*>(S + (size_t)j * ns + col0 + 2 * c);
-    z[w] = scale(x, ta.aj[j]);
+  const size_t ns = ta.ns;
+  constexpr int W = NTT * C, IT = cdiv_i(W, NT);
+  {
+    // issue every load of the tile before using any (latency hiding)
+    cx<T> x[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (W % NT == 0 || w < W) {
+        const int j = w / C, c = w - (w / C) * C;
+        x[i] = *reinterpret_cast<const cx<T>*>(S + j * ns + col0 + 2 * c);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (W % NT == 0 || w < W) z[w] = scale(x[i], ta.aj[w / C]);
+    }
   }
   __syncthreads();
-  fft_lds<T, NTT, C, C, NT, -1>(z, ta.tw);
-  const T cb = ta.cbar_mode ? T(ta.cbar ? *ta.cbar : ta.cbar_val) : T(0);
-  constexpr int WD = (NTT / 2 + 1) * C;
-  for (int w = tid; w < WD; w += NT) {
+  fft_lds<T, NTT, C, C, NT, -1>(z, s_tw);
+  constexpr int WD = (NTT / 2 + 1) * C, ITD = cdiv_i(WD, NT);
+  // coefficients of every (l, c) item of this thread, loaded together
+  cx<T> l1v[ITD], plv[ITD], qlv[ITD];
+  T lk1v[ITD], lk2v[ITD];
+  const double cbd = ta.cbar_mode ? (ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0;
+#pragma unroll
+  for (int i = 0; i < ITD; ++i) {
+    const int w = tid + i * NT;
+    const int l = w < WD ? w / C : 0, c = w - (w / C) * C;
+    const int k1 = col0 + 2 * c, k2 = k1 + 1;
+    l1v[i] = ta.lam1[l];
+    plv[i] = ta.pco[l];
+    qlv[i] = ta.qco[l];
+    lk1v[i] = ta.lamx[k1 % ta.nx] + ta.lamy[k1 / ta.nx];
+    lk2v[i] = ta.lamx[k2 % ta.nx] + ta.lamy[k2 / ta.nx];
+  }
+  const T cb = T(cbd);
+#pragma unroll
+  for (int i = 0; i < ITD; ++i) {
+    const int w = tid + i * NT;
+    if (w >= WD) continue;
     const int l = w / C, c = w - (w / C) * C;
     const int m = (NTT - l) & (NTT - 1);
     const cx<T> zl = z[l * C + c];
     const cx<T> zm = conj(z[m * C + c]);
     const cx<T> x1 = scale(add(zl, zm), T(0.5));
     const cx<T> x2 = scale(mul_mi(sub(zl, zm)), T(0.5));
-    const int k1 = col0 + 2 * c, k2 = k1 + 1;
-    const T lk1 = ta.lamx[k1 % ta.nx] + ta.lamy[k1 / ta.nx];
-    const T lk2 = ta.lamx[k2 % ta.nx] + ta.lamy[k2 / ta.nx];
-    const cx<T> l1 = ta.lam1[l];
-    const cx<T> pl = mk(ta.pco[l].x - cb, ta.pco[l].y);
-    const cx<T> ql = ta.qco[l];
+    const T lk1 = lk1v[i], lk2 = lk2v[i];
+    const cx<T> l1 = l1v[i];
+    const cx<T> pl = mk(plv[i].x - cb, plv[i].y);
+    const cx<T> ql = qlv[i];
     const cx<T> s1 = mk(l1.x + pl.x * lk1 + ql.x * lk1 * lk1, l1.y + pl.y * lk1 + ql.y * lk1 * lk1);
     const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2 * lk2, l1.y + pl.y * lk2 + ql.y * lk2 * lk2);
     const cx<T> y1 = cdiv(x1, s1);
@@ -271,28 +564,36 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     if (m != l) z[m * C + c] = add(conj(y1), mul_i(conj(y2)));
   }
   __syncthreads();
-  fft_lds<T, NTT, C, C, NT, +1>(z, ta.tw);
-  for (int w = tid; w < W; w += NT) {
-    const int j = w / C, c = w - (w / C) * C;
-    *reinterpret_cast<cx<T>*>(S + (size_t)j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+  fft_lds<T, NTT, C, C, NT, +1>(z, s_tw);
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int w = tid + i * NT;
+    if (W % NT == 0 || w < W) {
+      const int j = w / C, c = w - (w / C) * C;
+      *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+    }
   }
 }
 
-// --------------------------------------------------------------- control
-// One workgroup: reduce the per-level partials in a fixed order, update the
-// scalar averaged Jacobian and apply the stop rule.
+// ---------------------------------------------------------------------------
+// a7.  One workgroup: per level, sum the block partials; then max over levels
 //   upd  = max_n ||delta_n||_2,  unrm = max_n ||u_n||_2,  rel = upd / unrm
 //   rho  = upd_k / upd_{k-1};  est = rho/(1-rho) * rel
-// stop when est <= 0.1 rtol (k >= 2, rho < 1) or rel <= 1e-3 rtol;
+// stop when est <= safety * rtol (k >= 2, rho < 1) or rel <= 1e-3 rtol;
 // diverged on NaN/Inf or when the update grows 1e3-fold over the first one.
-__global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
-  if (f.ctrl->done) return;
-  constexpr int NT = 256;
-  __shared__ double red[4 * NT];
+// The scalar averaged Jacobian for the next time solve is mean(3 u^2).
+template <int NT>
+__device__ void finalize_body(const FinArgs& f, double* red) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // max dsq, max usq, sum u2, max rsq
   for (int n = threadIdx.x; n < f.nt; n += NT) {
-    const double* pp = f.part + (size_t)n * PART_STRIDE;
-    const double dsq = pp[PART_DSQ], usq = pp[PART_USQ], u2 = pp[PART_U2], rsq = pp[PART_RSQ];
+    double dsq = 0.0, usq = 0.0, u2 = 0.0, rsq = 0.0;
+    for (int bb = 0; bb < f.nbl; ++bb) {
+      const double* pp = f.part + (size_t(n) * f.nbl + bb) * PART_STRIDE;
+      dsq += pp[PART_DSQ];
+      usq += pp[PART_USQ];
+      u2 += pp[PART_U2];
+      rsq += pp[PART_RSQ];
+    }
     v[0] = (dsq != dsq || dsq > v[0]) ? dsq : v[0];
     v[1] = (usq != usq || usq > v[1]) ? usq : v[1];
     v[2] += u2;
@@ -325,84 +626,92 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
   if (bad || (k >= 2 && upd > 1e3 * c->upd_first)) {
     c->status = PINT_EDIVERGED;
     c->done = 1;
-  } else if (est <= 0.1 * f.rtol || rel <= 1e-3 * f.rtol) {
+  } else if (est <= f.safety * f.rtol || rel <= 1e-3 * f.rtol) {
     c->status = PINT_OK;
     c->done = 1;
   } else if (k + 1 >= f.max_iter) {
     c->status = PINT_ENOCONV;
     c->done = 1;
   }
+  if (f.host) {
+    // status mirror in pinned host memory: read by the host after the stream
+    // synchronizes, so no device-to-host copy is needed per check
+    Ctrl* h = f.host;
+    if (k < PINT_HIST_DEV) {
+      h->upd_hist[k] = rel;
+      h->res_hist[k] = res;
+    }
+    h->iter = k + 1;
+    h->c_bar = cbar;
+    h->est = est;
+    h->status = c->status;
+    h->done = c->done;
+  }
 }
 
-// Partial sums of 3 u^2 over the initial guess (the first iteration's c_bar),
-// optionally broadcasting u0 into U first.  One workgroup per level.
-__global__ __launch_bounds__(256) void k_init(InitArgs a) {
-  constexpr int NT = 256;
+// Stand-alone control kernel (one workgroup), used when the update kernel
+// does not run it itself.
+__global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
+  if (f.ctrl->done) return;
+  __shared__ double red[4 * 256];
+  finalize_body<256>(f, red);
+}
+
+// Control record reset and the first iteration's c_bar = mean(3 u^2) of the
+// initial guess (CH operators only): k_init_part writes workgroup partial
+// sums of 3 u^2 over u0 (broadcast guess) or over U, k_init_ctrl adds them
+// in a fixed order.
+constexpr int INIT_CHUNK = 4096;  // values per workgroup of k_init_part
+
+__global__ __launch_bounds__(256) void k_init_part(InitArgs a) {
+  constexpr int NT = 256, PER = INIT_CHUNK / NT;
   __shared__ double red[NT];
-  const int n = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < a.ns; i += NT) {
-    double u;
-    if (a.broadcast) {
-      u = a.u0[i];
-      a.U[(size_t)n * a.ns + i] = u;
-    } else {
-      u = a.U[(size_t)n * a.ns + i];
-    }
-    s += 3.0 * u * u;
+  const double* src = a.broadcast ? a.u0 : a.U;
+  const size_t total = a.broadcast ? size_t(a.ns) : size_t(a.ns) * a.nt;
+  const size_t base = size_t(blockIdx.x) * INIT_CHUNK;
+  double x[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const size_t j = base + threadIdx.x + size_t(i) * NT;
+    x[i] = j < total ? src[j] : 0.0;
   }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) s += 3.0 * x[i] * x[i];
   double v[1] = {s};
   const bool ismax[1] = {false};
   block_reduce<NT, 1>(red, v, ismax);
-  if (threadIdx.x == 0) a.part[(size_t)n * PART_STRIDE + PART_U2] = v[0];
+  if (threadIdx.x == 0) a.part[size_t(blockIdx.x) * PART_STRIDE + PART_U2] = v[0];
 }
 
-__global__ __launch_bounds__(64) void k_init_ctrl(Ctrl* c, int nt, const double* part, double dof) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_init_ctrl(Ctrl* c, Ctrl* host, InitArgs a, double dof, int nparts) {
+  constexpr int NT = 256;
+  __shared__ double red[NT];
   double s = 0.0;
-  for (int n = 0; n < nt; ++n) s += part[(size_t)n * PART_STRIDE + PART_U2];
+  for (int i = threadIdx.x; i < nparts; i += NT) s += a.part[size_t(i) * PART_STRIDE + PART_U2];
+  double v[1] = {s};
+  const bool ismax[1] = {false};
+  block_reduce<NT, 1>(red, v, ismax);
+  if (threadIdx.x != 0) return;
   c->iter = 0;
   c->done = 0;
   c->status = PINT_ENOCONV;
-  c->c_bar = s / dof;
+  c->c_bar = nparts ? (a.broadcast ? v[0] / a.ns : v[0] / dof) : 0.0;
   c->upd_prev = 0.0;
   c->upd_first = 0.0;
   c->est = 1e300;
+  if (host) {
+    host->iter = 0;
+    host->done = 0;
+    host->status = PINT_ENOCONV;
+  }
 }
 
 // ------------------------------------------------------------- stage I/O
-template <typename T>
-__global__ void k_cast_to(const double* __restrict__ in, T* __restrict__ out, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = T(in[i]);
-}
-template <typename T>
-__global__ void k_cast_from(const T* __restrict__ in, double* __restrict__ out, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = double(in[i]);
-}
-
-// Stand-alone batched DCT (stage entry point): one level (2D) or ROWS
-// levels (1D) per workgroup.
-template <typename T, int DIM, int N, int ROWS, int NT, bool INV>
-__global__ __launch_bounds__(NT) void k_dct(const T* __restrict__ in, T* __restrict__ out, DctTables<T> dt) {
-  constexpr int NPT = N * ROWS / NT;
-  __shared__ __align__(16) unsigned char lds[slice_lds<T, N, ROWS>::value];
-  T* A = reinterpret_cast<T*>(lds);
-  const int tid = threadIdx.x;
-  const size_t base = (size_t)blockIdx.x * N * ROWS;
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) A[tid + i * NT] = in[base + tid + i * NT];
-  __syncthreads();
-  if (!INV) {
-    dct2_rows<T, N, ROWS, N, NT>(A, dt.tw, dt.wq);
-    if (DIM == 2) dct2_cols<T, N, N, NT>(A, dt.tw, dt.wq);
-  } else {
-    if (DIM == 2) dct3_cols<T, N, N, NT>(A, dt.tw, dt.wi);
-    dct3_rows<T, N, ROWS, N, NT>(A, dt.tw, dt.wi);
-  }
-#pragma unroll
-  for (int i = 0; i < NPT; ++i) out[base + tid + i * NT] = A[tid + i * NT];
+template <typename TI, typename TO>
+__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = TO(in[i]);
 }
 
 // Per-level mass and Ginzburg-Landau energy (FP64).  One workgroup per level.
@@ -410,7 +719,7 @@ __global__ __launch_bounds__(256) void k_diagnostics(DiagArgs a) {
   constexpr int NT = 256;
   __shared__ double red[2 * NT];
   const int n = blockIdx.x;
-  const double* u = a.U + (size_t)n * a.ns;
+  const double* u = a.U + size_t(n) * a.ns;
   double m = 0.0, e = 0.0;
   for (int i = threadIdx.x; i < a.ns; i += NT) {
     const int x = i % a.nx, y = i / a.nx;
@@ -420,11 +729,11 @@ __global__ __launch_bounds__(256) void k_diagnostics(DiagArgs a) {
     e += 0.25 * w * w;
     double gsq = 0.0;
     if (x + 1 < a.nx) {
-      const double dd = (u[i + 1] - v);
+      const double dd = u[i + 1] - v;
       gsq += dd * dd;
     }
     if (a.dim == 2 && y + 1 < a.nx) {
-      const double dd = (u[i + a.nx] - v);
+      const double dd = u[i + a.nx] - v;
       gsq += dd * dd;
     }
     e += 0.5 * a.eps2 * gsq * a.inv_h2;
@@ -438,122 +747,186 @@ __global__ __launch_bounds__(256) void k_diagnostics(DiagArgs a) {
   }
 }
 
-// ------------------------------------------------------------- launchers
-#define PINT_CHECK_LAUNCH()                                                \
-  do {                                                                     \
-    hipError_t e_ = hipGetLastError();                                     \
-    if (e_ != hipSuccess) return e_;                                       \
+// ============================================================== launchers
+#define PINT_CHECK_LAUNCH()            \
+  do {                                 \
+    hipError_t e_ = hipGetLastError(); \
+    if (e_ != hipSuccess) return e_;   \
   } while (0)
 
-// Threads per workgroup of the per-level kernels: 2D levels by N; 1D slabs of
-// two levels with one thread per point (at least one wavefront of 64).
+// Row-pass geometry per grid size: rows per block and threads per block.
 template <int DIM, int N>
-struct slab_cfg {
-  static constexpr int ROWS = DIM == 2 ? N : 2;
-  static constexpr int NT0 = DIM == 2 ? slice_threads(N) : (N >= 64 ? N : 64);
-  static constexpr int NT = N * ROWS < NT0 ? N * ROWS : NT0;
-  static_assert((N * ROWS) % NT == 0, "threads must divide the slab");
+struct row_cfg {
+  static constexpr int RB = DIM == 1 ? 4 : (N >= 512 ? 8 : (N >= 256 ? 16 : (N >= 32 ? 32 : N)));
+  static constexpr int NT0 = 256;
+  static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
+  static constexpr int NBL = DIM == 2 ? N / RB : 1;
+};
+// Column-pass tile width and threads.
+template <int N>
+struct col_cfg {
+  static constexpr int XB = N < 32 ? N : 32;
+  static constexpr int NT = (N * XB / 2) < 256 ? (N * XB / 2) : 256;
 };
 
-template <typename T, int DIM, int N>
-static hipError_t launch_resid_n(const ResidArgs& a, T* S, double* rout, const DctTables<T>& dt, int nt, int mode,
-                                 hipStream_t st) {
-  using C = slab_cfg<DIM, N>;
-  const int grid = DIM == 2 ? nt : nt / C::ROWS;
+int rows_blocks_per_level(int dim, int n) {
+  if (dim == 1) return 1;
+  switch (n) {
+    case 8: return row_cfg<2, 8>::NBL;
+    case 16: return row_cfg<2, 16>::NBL;
+    case 32: return row_cfg<2, 32>::NBL;
+    case 64: return row_cfg<2, 64>::NBL;
+    case 128: return row_cfg<2, 128>::NBL;
+    case 256: return row_cfg<2, 256>::NBL;
+    case 512: return row_cfg<2, 512>::NBL;
+    default: return 0;
+  }
+}
+
+int rows_levels_per_block(int dim, int n) {
+  (void)n;
+  return dim == 1 ? row_cfg<1, 8>::RB : 1;
+}
+
+template <typename T, typename TO, int DIM, int N>
+static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+                                    int mode, hipStream_t st) {
+  using C = row_cfg<DIM, N>;
+  const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
-    hipLaunchKernelGGL((k_resid_dct<T, DIM, N, C::ROWS, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, rout, dt);
+    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, rout,
+                       dt);
   else
-    hipLaunchKernelGGL((k_resid_dct<T, DIM, N, C::ROWS, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, rout, dt);
+    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, rout,
+                       dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
 template <typename T, int DIM, int N>
-static hipError_t launch_upd_n(const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt, int nt, int mode,
-                               hipStream_t st) {
-  using C = slab_cfg<DIM, N>;
-  const int grid = DIM == 2 ? nt : nt / C::ROWS;
+static hipError_t launch_rows_inv_n(const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt, int nt,
+                                    int mode, hipStream_t st) {
+  using C = row_cfg<DIM, N>;
+  const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
-    hipLaunchKernelGGL((k_idct_update<T, DIM, N, C::ROWS, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
+    hipLaunchKernelGGL((k_rows_inv<T, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
   else
-    hipLaunchKernelGGL((k_idct_update<T, DIM, N, C::ROWS, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
+    hipLaunchKernelGGL((k_rows_inv<T, DIM, N, C::RB, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
 template <typename T, int DIM, int N>
-static hipError_t launch_dct_n(const T* in, T* out, const DctTables<T>& dt, int nt, bool inv, hipStream_t st) {
-  using C = slab_cfg<DIM, N>;
-  const int grid = DIM == 2 ? nt : nt / C::ROWS;
+static hipError_t launch_rows_dct_n(const T* in, T* out, const DctTables<T>& dt, int nt, bool inv, hipStream_t st) {
+  using C = row_cfg<DIM, N>;
+  const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (!inv)
-    hipLaunchKernelGGL((k_dct<T, DIM, N, C::ROWS, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
+    hipLaunchKernelGGL((k_rows_dct<T, DIM, N, C::RB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
   else
-    hipLaunchKernelGGL((k_dct<T, DIM, N, C::ROWS, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
+    hipLaunchKernelGGL((k_rows_dct<T, DIM, N, C::RB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-// Sizes of the per-slice path: 2D N in [8, 128]; 1D N in [8, 512].
-#define PINT_SWITCH_N(DIM, CALL)                        \
-  switch (n) {                                          \
-    case 8: return CALL(DIM, 8);                        \
-    case 16: return CALL(DIM, 16);                      \
-    case 32: return CALL(DIM, 32);                      \
-    case 64: return CALL(DIM, 64);                      \
-    case 128: return CALL(DIM, 128);                    \
-    default: break;                                     \
+template <typename T, typename TO, int N>
+static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
+                                hipStream_t st) {
+  using C = col_cfg<N>;
+  const int grid = nt * (N / C::XB);
+  if (!inv)
+    hipLaunchKernelGGL((k_cols<T, TO, N, C::XB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
+  else if constexpr (std::is_same<T, TO>::value)
+    hipLaunchKernelGGL((k_cols<T, TO, N, C::XB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
+  else
+    return hipErrorInvalidValue;
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+#define PINT_SWITCH_N(CALL)               \
+  switch (n) {                            \
+    case 8: return CALL(8);               \
+    case 16: return CALL(16);             \
+    case 32: return CALL(32);             \
+    case 64: return CALL(64);             \
+    case 128: return CALL(128);           \
+    case 256: return CALL(256);           \
+    case 512: return CALL(512);           \
+    default: return hipErrorInvalidValue; \
   }
 
-template <typename T>
-hipError_t launch_resid(int dim, int n, const ResidArgs& a, T* S, double* rout, const DctTables<T>& dt, int nt,
-                        int mode, hipStream_t st) {
-#define C_(D, NN) launch_resid_n<T, D, NN>(a, S, rout, dt, nt, mode, st)
-  if (dim == 2) { PINT_SWITCH_N(2, C_) }
-  else {
-    PINT_SWITCH_N(1, C_)
-    if (n == 256) return C_(1, 256);
-    if (n == 512) return C_(1, 512);
+template <typename T, typename TO>
+hipError_t launch_rows_fwd(int dim, int n, const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+                           int mode, hipStream_t st) {
+#define C1_(NN) launch_rows_fwd_n<T, TO, 1, NN>(a, S, rout, dt, nt, mode, st)
+#define C2_(NN) launch_rows_fwd_n<T, TO, 2, NN>(a, S, rout, dt, nt, mode, st)
+  if (dim == 2) {
+    PINT_SWITCH_N(C2_)
   }
-#undef C_
-  return hipErrorInvalidValue;
+  PINT_SWITCH_N(C1_)
+#undef C1_
+#undef C2_
 }
 
 template <typename T>
-hipError_t launch_update(int dim, int n, const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt, int nt,
-                         int mode, hipStream_t st) {
-#define C_(D, NN) launch_upd_n<T, D, NN>(a, S, dout, dt, nt, mode, st)
-  if (dim == 2) { PINT_SWITCH_N(2, C_) }
-  else {
-    PINT_SWITCH_N(1, C_)
-    if (n == 256) return C_(1, 256);
-    if (n == 512) return C_(1, 512);
+hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt,
+                           int nt, int mode, hipStream_t st) {
+#define C1_(NN) launch_rows_inv_n<T, 1, NN>(a, S, dout, dt, nt, mode, st)
+#define C2_(NN) launch_rows_inv_n<T, 2, NN>(a, S, dout, dt, nt, mode, st)
+  if (dim == 2) {
+    PINT_SWITCH_N(C2_)
   }
-#undef C_
-  return hipErrorInvalidValue;
+  PINT_SWITCH_N(C1_)
+#undef C1_
+#undef C2_
 }
 
+template <typename T, typename TO>
+hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
+                       hipStream_t st) {
+#define CC_(NN) launch_cols_n<T, TO, NN>(Sin, Sout, done, dt, nt, inv, st)
+  PINT_SWITCH_N(CC_)
+#undef CC_
+}
+
+template <typename T, int DIM>
+static hipError_t rows_dct_dispatch(int n, const T* in, T* out, const DctTables<T>& dt, int nt, bool inv,
+                                    hipStream_t st) {
+#define RR_(NN) launch_rows_dct_n<T, DIM, NN>(in, out, dt, nt, inv, st)
+  PINT_SWITCH_N(RR_)
+#undef RR_
+}
+
+// Stage entry: orthonormal DCT-II (or its inverse) of every level; in == out
+// allowed.  2D forward = rows then columns; inverse = columns then rows.
 template <typename T>
 hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& dt, int nt, bool inv,
                       hipStream_t st) {
-#define C_(D, NN) launch_dct_n<T, D, NN>(in, out, dt, nt, inv, st)
-  if (dim == 2) { PINT_SWITCH_N(2, C_) }
-  else {
-    PINT_SWITCH_N(1, C_)
-    if (n == 256) return C_(1, 256);
-    if (n == 512) return C_(1, 512);
+  if (dim == 1) return rows_dct_dispatch<T, 1>(n, in, out, dt, nt, inv, st);
+  hipError_t e;
+  if (!inv) {
+    e = rows_dct_dispatch<T, 2>(n, in, out, dt, nt, false, st);
+    if (e != hipSuccess) return e;
+    return launch_cols<T, T>(n, out, out, nullptr, dt, nt, false, st);
   }
-#undef C_
-  return hipErrorInvalidValue;
+  if (in != out) {
+    e = hipMemcpyAsync(out, in, sizeof(T) * size_t(nt) * n * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_cols<T, T>(n, out, out, nullptr, dt, nt, true, st);
+  if (e != hipSuccess) return e;
+  return rows_dct_dispatch<T, 2>(n, out, out, dt, nt, true, st);
 }
 
 // Time solve: tile width M (spatial modes per workgroup) is the largest of
 // {8, 16, 32, 64} that divides ns and keeps the LDS tile (N_t x M/2 complex)
-// within 64 KB, so that two workgroups can share a CU.
+// within 64 KB; TimeArgs::tile can cap it.
 template <typename T, int NTT>
 struct time_cfg {
   static constexpr int BYTES = NTT * int(sizeof(cx<T>));  // one complex column
   static constexpr int CMAX0 = 65536 / BYTES;
   static constexpr int MMAX = 2 * (CMAX0 < 32 ? CMAX0 : 32);
+  static constexpr int MDEF = MMAX < 32 ? MMAX : 32;
 };
 
 template <typename T, int NTT, int M>
@@ -569,7 +942,8 @@ static hipError_t launch_time_m(T* S, const TimeArgs<T>& ta, hipStream_t st) {
 
 template <typename T, int NTT>
 static hipError_t launch_time_nt(T* S, const TimeArgs<T>& ta, hipStream_t st) {
-  int m = time_cfg<T, NTT>::MMAX;
+  int m = time_cfg<T, NTT>::MDEF;
+  if (ta.tile > 0) m = ta.tile < time_cfg<T, NTT>::MMAX ? ta.tile : time_cfg<T, NTT>::MMAX;
   while (m > 8 && (m > ta.ns || ta.ns % m != 0)) m /= 2;
   if (ta.ns % m != 0) return hipErrorInvalidValue;
   switch (m) {
@@ -603,23 +977,22 @@ hipError_t launch_finalize(const FinArgs& f, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_init(const InitArgs& a, Ctrl* c, double dof, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(a.nt), dim3(256), 0, st, a);
-  PINT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, st, c, a.nt, (const double*)a.part, dof);
+hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool need_cbar, hipStream_t st) {
+  int nparts = 0;
+  if (need_cbar) {
+    const size_t total = a.broadcast ? size_t(a.ns) : size_t(a.ns) * a.nt;
+    nparts = int((total + INIT_CHUNK - 1) / INIT_CHUNK);
+    hipLaunchKernelGGL(k_init_part, dim3(nparts), dim3(256), 0, st, a);
+    PINT_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(256), 0, st, c, host, a, dof, nparts);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-template <typename T>
-hipError_t launch_cast_to(const double* in, T* out, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_to<T>, dim3(1024), dim3(256), 0, st, in, out, n);
-  PINT_CHECK_LAUNCH();
-  return hipSuccess;
-}
-template <typename T>
-hipError_t launch_cast_from(const T* in, double* out, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_from<T>, dim3(1024), dim3(256), 0, st, in, out, n);
+template <typename TI, typename TO>
+hipError_t launch_cast(const TI* in, TO* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast<TI, TO>), dim3(1024), dim3(256), 0, st, in, out, n);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -630,23 +1003,29 @@ hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st) {
   return hipSuccess;
 }
 
-template hipError_t launch_resid<float>(int, int, const ResidArgs&, float*, double*, const DctTables<float>&, int,
-                                        int, hipStream_t);
-template hipError_t launch_resid<double>(int, int, const ResidArgs&, double*, double*, const DctTables<double>&, int,
-                                         int, hipStream_t);
-template hipError_t launch_update<float>(int, int, const UpdArgs&, const float*, double*, const DctTables<float>&,
-                                         int, int, hipStream_t);
-template hipError_t launch_update<double>(int, int, const UpdArgs&, const double*, double*,
-                                          const DctTables<double>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<float, float>(int, int, const ResidArgs&, float*, double*,
+                                                  const DctTables<float>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<double, double>(int, int, const ResidArgs&, double*, double*,
+                                                    const DctTables<double>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<double, float>(int, int, const ResidArgs&, float*, double*,
+                                                   const DctTables<double>&, int, int, hipStream_t);
+template hipError_t launch_rows_inv<float>(int, int, const UpdArgs&, const float*, double*, const DctTables<float>&,
+                                           int, int, hipStream_t);
+template hipError_t launch_rows_inv<double>(int, int, const UpdArgs&, const double*, double*,
+                                            const DctTables<double>&, int, int, hipStream_t);
+template hipError_t launch_cols<float, float>(int, const float*, float*, const int*, const DctTables<float>&, int,
+                                              bool, hipStream_t);
+template hipError_t launch_cols<double, double>(int, const double*, double*, const int*, const DctTables<double>&,
+                                                int, bool, hipStream_t);
+template hipError_t launch_cols<double, float>(int, const double*, float*, const int*, const DctTables<double>&,
+                                               int, bool, hipStream_t);
 template hipError_t launch_dct<float>(int, int, const float*, float*, const DctTables<float>&, int, bool,
                                       hipStream_t);
 template hipError_t launch_dct<double>(int, int, const double*, double*, const DctTables<double>&, int, bool,
                                        hipStream_t);
 template hipError_t launch_time<float>(int, float*, const TimeArgs<float>&, hipStream_t);
 template hipError_t launch_time<double>(int, double*, const TimeArgs<double>&, hipStream_t);
-template hipError_t launch_cast_to<float>(const double*, float*, size_t, hipStream_t);
-template hipError_t launch_cast_to<double>(const double*, double*, size_t, hipStream_t);
-template hipError_t launch_cast_from<float>(const float*, double*, size_t, hipStream_t);
-template hipError_t launch_cast_from<double>(const double*, double*, size_t, hipStream_t);
+template hipError_t launch_cast<double, float>(const double*, float*, size_t, hipStream_t);
+template hipError_t launch_cast<double, double>(const double*, double*, size_t, hipStream_t);
 
 }  // namespace pint

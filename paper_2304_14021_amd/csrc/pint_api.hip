@@ -3,12 +3,15 @@
 // points.  Everything on the hot path runs in the kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pint.h"
@@ -37,7 +40,11 @@ struct pint_plan {
   int dim, n, nt, ns;
   double h, alpha, a, dof, rtol;
   int max_iter;
-  bool fp64;  // working precision W = double
+  int nbl;          // row blocks per level (2D), 1 in 1D
+  int predict = 2;  // iterations enqueued before the first stop-flag check
+  double safety = 0.1;
+  bool fp64;   // working precision W = double
+  bool mixed;  // FP64 forward spatial transform, FP32 time solve and inverse
   std::string err;
 
   // device tables (one allocation), FP64 then FP32 copies
@@ -49,12 +56,12 @@ struct pint_plan {
   TimeArgs<float> taf{};
   ResidArgs ra{};
 
-  int* h_flag = nullptr;  // pinned 4-byte stop flag readback
+  Ctrl* h_ctrl = nullptr;  // pinned host mirror written by the control kernel
   std::vector<hipEvent_t> ev;
 
   ~pint_plan() {
     if (d_tab) (void)hipFree(d_tab);
-    if (h_flag) (void)hipHostFree(h_flag);
+    if (h_ctrl) (void)hipHostFree(h_ctrl);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -96,7 +103,6 @@ int validate(const pint_problem* p, std::string* err) {
   if (!is_pow2(p->nx) || p->nx < 8 || p->nx > 512)
     return set_err(err, PINT_EINVAL, "nx must be a power of two in [8, 512]");
   if (p->dim == 2 && p->ny != p->nx) return set_err(err, PINT_EINVAL, "2D grids must be square (ny == nx)");
-  if (p->dim == 2 && p->nx > 128) return set_err(err, PINT_EINVAL, "2D grids above 128^2 are not built yet");
   if (p->dim == 1 && p->ny != 1 && p->ny != 0) return set_err(err, PINT_EINVAL, "1D problems need ny == 1");
   if (!is_pow2(p->nt) || p->nt < 4 || p->nt > 1024)
     return set_err(err, PINT_EINVAL, "nt must be a power of two in [4, 1024]");
@@ -107,7 +113,7 @@ int validate(const pint_problem* p, std::string* err) {
     return set_err(err, PINT_EINVAL, "the CH schemes are backward Euler (theta = 1)");
   if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
   if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
-  if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE)
+  if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED)
     return set_err(err, PINT_EINVAL, "precision not supported by this build");
   if (p->time_path != PINT_TIME_AUTO && p->time_path != PINT_TIME_FFT)
     return set_err(err, PINT_EINVAL, "time path not supported by this build");
@@ -237,18 +243,29 @@ void bind(const Offs& o, unsigned char* base, const pint_plan* pl, DctTables<T>&
   ta.cbar_mode = (pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE) ? 1 : 0;
   ta.cbar = nullptr;
   ta.done = nullptr;
+  // tuning override of the time-solve tile width (spatial modes per workgroup)
+  const char* tile = std::getenv("PINT_TIME_TILE");
+  ta.tile = tile ? std::atoi(tile) : 0;
 }
 
 struct Work {
-  void* S;
+  void* S;    // spectral scratch in the working type W
+  void* S64;  // FP64 forward-transform scratch (mixed precision only)
   double* part;
   Ctrl* ctrl;
 };
 
+// Partial-result slots: one per [level][row block]; the initial c_bar
+// reduction needs one per 4096 values of the initial guess.
+size_t part_bytes(const pint_plan* pl) {
+  const size_t slots = std::max<size_t>((size_t)pl->nt * pl->nbl, ((size_t)pl->nt * pl->ns + 4095) / 4096);
+  return align256(slots * PART_STRIDE * 8);
+}
+size_t s_bytes(const pint_plan* pl) { return align256((size_t)pl->nt * pl->ns * (pl->fp64 ? 8 : 4)); }
+size_t s64_bytes(const pint_plan* pl) { return pl->mixed ? align256((size_t)pl->nt * pl->ns * 8) : 0; }
+
 size_t work_size(const pint_plan* pl) {
-  const size_t wb = pl->fp64 ? 8 : 4;
-  return align256((size_t)pl->nt * pl->ns * wb) + align256((size_t)pl->nt * PART_STRIDE * 8) +
-         align256(sizeof(Ctrl));
+  return s_bytes(pl) + s64_bytes(pl) + part_bytes(pl) + align256(sizeof(Ctrl));
 }
 
 int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
@@ -256,12 +273,13 @@ int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
   if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
     return set_err(&pl->err, PINT_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < work_size(pl)) return set_err(&pl->err, PINT_ENOMEM, "workspace smaller than pint_plan_workspace_size");
-  const size_t wb = pl->fp64 ? 8 : 4;
   unsigned char* b = static_cast<unsigned char*>(d_work);
   w.S = b;
-  b += align256((size_t)pl->nt * pl->ns * wb);
+  b += s_bytes(pl);
+  w.S64 = pl->mixed ? b : nullptr;
+  b += s64_bytes(pl);
   w.part = reinterpret_cast<double*>(b);
-  b += align256((size_t)pl->nt * PART_STRIDE * 8);
+  b += part_bytes(pl);
   w.ctrl = reinterpret_cast<Ctrl*>(b);
   return PINT_OK;
 }
@@ -276,12 +294,30 @@ int hip_fail(pint_plan* pl, hipError_t e, const char* what) {
     if (e__ != hipSuccess) return hip_fail(pl, e__, what); \
   } while (0)
 
-// Enqueue one outer iteration.
+constexpr int EV_PER_IT = 7;  // events bracketing the 6 kernels of one iteration
+
 template <typename T>
+const DctTables<T>& dct_tables(const pint_plan* pl);
+template <>
+const DctTables<double>& dct_tables<double>(const pint_plan* pl) { return pl->dtd; }
+template <>
+const DctTables<float>& dct_tables<float>(const pint_plan* pl) { return pl->dtf; }
+template <typename T>
+TimeArgs<T> time_args(const pint_plan* pl);
+template <>
+TimeArgs<double> time_args<double>(const pint_plan* pl) { return pl->tad; }
+template <>
+TimeArgs<float> time_args<float>(const pint_plan* pl) { return pl->taf; }
+
+// Enqueue one outer iteration: row pass (residual + x-DCT), column pass
+// (y-DCT), time solve, column pass (y-DCT-III), row pass (x-DCT-III + update),
+// control.  TF is the type of the forward spatial transform, T that of the
+// time solve and the inverse transform.  bcast: the iterate is the broadcast
+// datum u0 (first iteration).
+template <typename TF, typename T>
 int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st,
-                      hipEvent_t* evs) {
-  const DctTables<T>& dt = *reinterpret_cast<const DctTables<T>*>(pl->fp64 ? (void*)&pl->dtd : (void*)&pl->dtf);
-  TimeArgs<T> ta = *reinterpret_cast<const TimeArgs<T>*>(pl->fp64 ? (void*)&pl->tad : (void*)&pl->taf);
+                      hipEvent_t* evs, bool bcast) {
+  TimeArgs<T> ta = time_args<T>(pl);
   ta.cbar = &w.ctrl->c_bar;
   ta.done = &w.ctrl->done;
   ResidArgs ra = pl->ra;
@@ -289,19 +325,42 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.U = d_U;
   ra.part = w.part;
   ra.done = &w.ctrl->done;
-  UpdArgs ua{d_U, w.part, &w.ctrl->done};
-  FinArgs fa{w.ctrl, w.part, pl->nt, pl->max_iter, pl->dof, pl->rtol};
+  ra.bcast = bcast ? 1 : 0;
+  FinArgs fa{w.ctrl, pl->h_ctrl, w.part, pl->nt, pl->nbl, pl->max_iter, pl->dof, pl->rtol, pl->safety};
+  UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0};
   T* S = static_cast<T*>(w.S);
-  if (evs) HIPCHK(hipEventRecord(evs[0], st), "hipEventRecord");
-  HIPCHK(launch_resid<T>(pl->dim, pl->n, ra, S, nullptr, dt, pl->nt, 0, st), "residual kernel");
-  if (evs) HIPCHK(hipEventRecord(evs[1], st), "hipEventRecord");
+  TF* SF = std::is_same<TF, T>::value ? reinterpret_cast<TF*>(w.S) : static_cast<TF*>(w.S64);
+  const int* done = &w.ctrl->done;
+  auto ev = [&](int i) -> hipError_t { return evs ? hipEventRecord(evs[i], st) : hipSuccess; };
+  HIPCHK(ev(0), "hipEventRecord");
+  if (pl->dim == 2)
+    HIPCHK((launch_rows_fwd<TF, TF>(2, pl->n, ra, SF, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
+           "residual + x-DCT kernel");
+  else
+    HIPCHK((launch_rows_fwd<TF, T>(1, pl->n, ra, S, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
+           "residual + x-DCT kernel");
+  HIPCHK(ev(1), "hipEventRecord");
+  if (pl->dim == 2)
+    HIPCHK((launch_cols<TF, T>(pl->n, SF, S, done, dct_tables<TF>(pl), pl->nt, false, st)), "y-DCT kernel");
+  HIPCHK(ev(2), "hipEventRecord");
   HIPCHK(launch_time<T>(pl->nt, S, ta, st), "time-solve kernel");
-  if (evs) HIPCHK(hipEventRecord(evs[2], st), "hipEventRecord");
-  HIPCHK(launch_update<T>(pl->dim, pl->n, ua, S, nullptr, dt, pl->nt, 0, st), "update kernel");
-  if (evs) HIPCHK(hipEventRecord(evs[3], st), "hipEventRecord");
-  HIPCHK(launch_finalize(fa, st), "finalize kernel");
-  if (evs) HIPCHK(hipEventRecord(evs[4], st), "hipEventRecord");
+  HIPCHK(ev(3), "hipEventRecord");
+  if (pl->dim == 2)
+    HIPCHK((launch_cols<T, T>(pl->n, S, S, done, dct_tables<T>(pl), pl->nt, true, st)), "y-DCT-III kernel");
+  HIPCHK(ev(4), "hipEventRecord");
+  HIPCHK(launch_rows_inv<T>(pl->dim, pl->n, ua, S, nullptr, dct_tables<T>(pl), pl->nt, 0, st),
+         "x-DCT-III + update kernel");
+  HIPCHK(ev(5), "hipEventRecord");
+  HIPCHK(launch_finalize(fa, st), "control kernel");
+  HIPCHK(ev(6), "hipEventRecord");
   return PINT_OK;
+}
+
+int enqueue_any(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st, hipEvent_t* evs,
+                bool bcast) {
+  if (pl->fp64) return enqueue_iteration<double, double>(pl, d_u0, d_U, w, st, evs, bcast);
+  if (pl->mixed) return enqueue_iteration<double, float>(pl, d_u0, d_U, w, st, evs, bcast);
+  return enqueue_iteration<float, float>(pl, d_u0, d_U, w, st, evs, bcast);
 }
 
 }  // namespace
@@ -346,6 +405,12 @@ int pint_plan_create(const pint_problem* p, pint_plan** out) {
   pl->rtol = p->rtol > 0 ? p->rtol : 1e-10;
   pl->max_iter = p->max_iter > 0 ? p->max_iter : 30;
   pl->fp64 = p->precision == PINT_PREC_FP64;
+  pl->mixed = p->precision == PINT_PREC_MIXED;
+  pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
+  if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {
+    delete pl;
+    return set_err(nullptr, PINT_EINVAL, "nt must be a multiple of the 1D levels per block");
+  }
   if (p->op == PINT_OP_CH || p->op == PINT_OP_CH_EYRE) pl->p.theta = 1.0;
 
   // Admissibility of alpha: the slowest-decaying (or fastest-growing) mode
@@ -410,9 +475,9 @@ int pint_plan_create(const pint_problem* p, pint_plan** out) {
   unsigned char* base = static_cast<unsigned char*>(pl->d_tab);
   bind<double>(od, base, pl, pl->dtd, pl->tad);
   bind<float>(of, base, pl, pl->dtf, pl->taf);
-  e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_flag), sizeof(int) * 4, hipHostMallocDefault);
+  e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_ctrl), sizeof(Ctrl), hipHostMallocCoherent);
   if (e != hipSuccess) {
-    rc = hip_fail(nullptr, e, "hipHostMalloc(flag)");
+    rc = hip_fail(nullptr, e, "hipHostMalloc(status mirror)");
     delete pl;
     return rc;
   }
@@ -451,36 +516,38 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool timing = (pl->p.flags & PINT_FLAG_STAGE_TIMING) != 0;
-  if (timing && pl->ev.size() < size_t(5 * pl->max_iter)) {
-    while (pl->ev.size() < size_t(5 * pl->max_iter)) {
+  if (timing && pl->ev.size() < size_t(EV_PER_IT * pl->max_iter)) {
+    while (pl->ev.size() < size_t(EV_PER_IT * pl->max_iter)) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e), "hipEventCreate");
       pl->ev.push_back(e);
     }
   }
-  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) ? 1 : 0};
-  HIPCHK(launch_init(ia, w.ctrl, pl->dof, st), "init kernels");
+  const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
+  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, pl->nbl, bcast ? 1 : 0};
+  const bool need_cbar = pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE;
+  HIPCHK(launch_init(ia, w.ctrl, pl->h_ctrl, pl->dof, need_cbar, st), "init kernels");
+  // Enqueue as many iterations as the previous solve of this plan needed
+  // (kernels after the device stop flag is set return at once), then check
+  // the flag after each further iteration.
   int it = 0;
+  const int first_check = std::min(std::max(pl->predict, 2), pl->max_iter);
   for (; it < pl->max_iter; ++it) {
-    hipEvent_t* evs = timing ? &pl->ev[5 * it] : nullptr;
-    rc = pl->fp64 ? enqueue_iteration<double>(pl, d_u0, d_U, w, st, evs)
-                  : enqueue_iteration<float>(pl, d_u0, d_U, w, st, evs);
+    hipEvent_t* evs = timing ? &pl->ev[EV_PER_IT * it] : nullptr;
+    rc = enqueue_any(pl, d_u0, d_U, w, st, evs, bcast && it == 0);
     if (rc) return rc;
-    // The stop rule cannot fire before the second iteration (it needs a
-    // contraction estimate), so the first check follows iteration 2.
-    if (it >= 1) {
-      HIPCHK(hipMemcpyAsync(pl->h_flag, &w.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    if (it + 1 >= first_check) {
       HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-      if (*pl->h_flag) {
+      if (reinterpret_cast<volatile int&>(pl->h_ctrl->done)) {
         ++it;
         break;
       }
     }
   }
-  Ctrl c;
-  HIPCHK(hipMemcpyAsync(&c, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
   HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+  const Ctrl& c = *pl->h_ctrl;
   const int status = c.done ? c.status : PINT_ENOCONV;
+  if (status == PINT_OK) pl->predict = c.iter;
   if (rep) {
     std::memset(reinterpret_cast<char*>(rep) + sizeof(size_t), 0, sizeof(pint_report) - sizeof(size_t));
     rep->status = status;
@@ -494,9 +561,9 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
     }
     if (timing) {
       for (int k = 0; k < c.iter && k < it; ++k)
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < EV_PER_IT - 1; ++s) {
           float ms = 0.f;
-          if (hipEventElapsedTime(&ms, pl->ev[5 * k + s], pl->ev[5 * k + s + 1]) == hipSuccess)
+          if (hipEventElapsedTime(&ms, pl->ev[EV_PER_IT * k + s], pl->ev[EV_PER_IT * k + s + 1]) == hipSuccess)
             rep->ms_stage[s] += ms;
         }
     }
@@ -520,10 +587,9 @@ int pint_residual(pint_plan* pl, const double* d_u0, const double* d_U, double* 
   ra.U = d_U;
   ra.part = w.part;
   ra.done = nullptr;
-  if (pl->fp64)
-    HIPCHK(launch_resid<double>(pl->dim, pl->n, ra, nullptr, d_r, pl->dtd, pl->nt, 1, st), "residual kernel");
-  else
-    HIPCHK(launch_resid<float>(pl->dim, pl->n, ra, nullptr, d_r, pl->dtf, pl->nt, 1, st), "residual kernel");
+  ra.bcast = 0;
+  HIPCHK((launch_rows_fwd<double, double>(pl->dim, pl->n, ra, nullptr, d_r, pl->dtd, pl->nt, 1, st)),
+         "residual kernel");
   return PINT_OK;
 }
 
@@ -566,24 +632,41 @@ int pint_precond_apply(pint_plan* pl, const double* d_r, double* d_delta, double
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t n = (size_t)pl->nt * pl->ns;
+  UpdArgs ua{nullptr, nullptr, w.part, nullptr, 0};
   if (pl->fp64) {
     double* S = static_cast<double*>(w.S);
-    HIPCHK(launch_cast_to<double>(d_r, S, n, st), "cast");
+    HIPCHK((launch_cast<double, double>(d_r, S, n, st)), "cast");
     HIPCHK(launch_dct<double>(pl->dim, pl->n, S, S, pl->dtd, pl->nt, false, st), "dct");
+  } else if (pl->mixed) {
+    // FP64 forward transform, rounded to FP32 after the last forward pass
+    double* S64 = static_cast<double*>(w.S64);
+    float* S = static_cast<float*>(w.S);
+    HIPCHK((launch_cast<double, double>(d_r, S64, n, st)), "cast");
+    if (pl->dim == 2) {
+      HIPCHK(launch_dct<double>(1, pl->n, S64, S64, pl->dtd, pl->nt * pl->n, false, st), "x-dct");
+      HIPCHK((launch_cols<double, float>(pl->n, S64, S, nullptr, pl->dtd, pl->nt, false, st)), "y-dct");
+    } else {
+      HIPCHK(launch_dct<double>(1, pl->n, S64, S64, pl->dtd, pl->nt, false, st), "x-dct");
+      HIPCHK((launch_cast<double, float>(S64, S, n, st)), "cast");
+    }
   } else {
     float* S = static_cast<float*>(w.S);
-    HIPCHK(launch_cast_to<float>(d_r, S, n, st), "cast");
+    HIPCHK((launch_cast<double, float>(d_r, S, n, st)), "cast");
     HIPCHK(launch_dct<float>(pl->dim, pl->n, S, S, pl->dtf, pl->nt, false, st), "dct");
   }
   rc = pint_time_solve(pl, w.S, c_bar, stream);
   if (rc) return rc;
-  UpdArgs ua{nullptr, w.part, nullptr};
-  if (pl->fp64)
-    HIPCHK(launch_update<double>(pl->dim, pl->n, ua, static_cast<double*>(w.S), d_delta, pl->dtd, pl->nt, 1, st),
-           "inverse dct");
-  else
-    HIPCHK(launch_update<float>(pl->dim, pl->n, ua, static_cast<float*>(w.S), d_delta, pl->dtf, pl->nt, 1, st),
-           "inverse dct");
+  if (pl->fp64) {
+    double* S = static_cast<double*>(w.S);
+    if (pl->dim == 2)
+      HIPCHK((launch_cols<double, double>(pl->n, S, S, nullptr, pl->dtd, pl->nt, true, st)), "inverse y-dct");
+    HIPCHK(launch_rows_inv<double>(pl->dim, pl->n, ua, S, d_delta, pl->dtd, pl->nt, 1, st), "inverse x-dct");
+  } else {
+    float* S = static_cast<float*>(w.S);
+    if (pl->dim == 2)
+      HIPCHK((launch_cols<float, float>(pl->n, S, S, nullptr, pl->dtf, pl->nt, true, st)), "inverse y-dct");
+    HIPCHK(launch_rows_inv<float>(pl->dim, pl->n, ua, S, d_delta, pl->dtf, pl->nt, 1, st), "inverse x-dct");
+  }
   return PINT_OK;
 }
 

@@ -39,16 +39,27 @@ struct Ctrl {
 struct ResidArgs {
   const double* u0;
   const double* U;
-  double* part;
+  double* part;     // [level][block] partials
   const int* done;
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
+  int bcast;        // the iterate is u0 at every level (first iteration)
+};
+
+struct FinArgs {
+  Ctrl* ctrl;
+  Ctrl* host;  // pinned host mirror of the status fields (nullable)
+  const double* part;
+  int nt, nbl, max_iter;
+  double dof, rtol, safety;
 };
 
 struct UpdArgs {
   double* U;
+  const double* u0;
   double* part;
   const int* done;
+  int bcast;        // U_n = u0 + delta_n instead of U_n += delta_n
 };
 
 template <typename T>
@@ -72,20 +83,14 @@ struct TimeArgs {
   double cbar_val;    // value used when cbar is null
   const int* done;
   int nx, ns, cbar_mode;
-};
-
-struct FinArgs {
-  Ctrl* ctrl;
-  const double* part;
-  int nt, max_iter;
-  double dof, rtol;
+  int tile;           // cap on the spatial modes per workgroup (0 = automatic)
 };
 
 struct InitArgs {
   const double* u0;
-  double* U;
+  const double* U;
   double* part;
-  int nt, ns, broadcast;
+  int nt, ns, nbl, broadcast;
 };
 
 struct DiagArgs {
@@ -96,23 +101,35 @@ struct DiagArgs {
   double eps2, inv_h2, hd;
 };
 
+// Row blocks per level of the 2D row passes (1 in 1D), and levels per block
+// of the 1D row passes (1 in 2D).
+int rows_blocks_per_level(int dim, int n);
+int rows_levels_per_block(int dim, int n);
+
+// Forward row pass computing in T, storing the x-DCT in TO.
+template <typename T, typename TO>
+hipError_t launch_rows_fwd(int dim, int n, const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+                           int mode, hipStream_t st);
 template <typename T>
-hipError_t launch_resid(int dim, int n, const ResidArgs& a, T* S, double* rout, const DctTables<T>& dt, int nt,
-                        int mode, hipStream_t st);
-template <typename T>
-hipError_t launch_update(int dim, int n, const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt, int nt,
-                         int mode, hipStream_t st);
+hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt,
+                           int nt, int mode, hipStream_t st);
+// Column pass computing in T, reading Sin (T) and writing Sout (TO; TO == T
+// for the inverse).  Sin == Sout is allowed when TO == T.
+template <typename T, typename TO>
+hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& dt, int nt, bool inv,
                       hipStream_t st);
 template <typename T>
 hipError_t launch_time(int nt, T* S, const TimeArgs<T>& ta, hipStream_t st);
-template <typename T>
-hipError_t launch_cast_to(const double* in, T* out, size_t n, hipStream_t st);
-template <typename T>
-hipError_t launch_cast_from(const T* in, double* out, size_t n, hipStream_t st);
+template <typename TI, typename TO>
+hipError_t launch_cast(const TI* in, TO* out, size_t n, hipStream_t st);
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st);
-hipError_t launch_init(const InitArgs& a, Ctrl* c, double dof, hipStream_t st);
+// Reset the control record (and its host mirror); with need_cbar, also the
+// first iteration's scalar averaged Jacobian.  The partials of the c_bar
+// reduction use a.part (nparts <= ceil(total / 4096) slots).
+hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool need_cbar, hipStream_t st);
 hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st);
 
 }  // namespace pint

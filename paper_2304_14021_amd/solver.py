@@ -18,7 +18,9 @@ class Solver:
     Parameters follow the paper's problem statement: operator ("biharmonic",
     "linear_ch", "ch", "ch_eyre"), dimension, cells per dimension n, time
     levels nt, step dt, theta, eps, beta, PinT parameter alpha (0 = automatic),
-    precision ("fp64" or "fp32": FP32 transforms with FP64 refinement),
+    precision ("fp64"; "fp32": FP32 transforms with FP64 refinement; "mixed":
+    FP64 forward spatial transform, FP32 time solve and inverse transform,
+    FP64 refinement),
     relative tolerance and iteration cap.
     """
 
@@ -47,6 +49,9 @@ class Solver:
     def _work_ptr(self):
         p = self.work.data_ptr()
         return p + ((-p) % 256)
+
+    def _wdt(self):
+        return torch.float64 if self.plan.problem.precision == _pint.PRECISIONS["fp64"] else torch.float32
 
     def _stream(self):
         return torch.cuda.current_stream(self.device).cuda_stream
@@ -79,7 +84,7 @@ class Solver:
         return r
 
     def dct(self, x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
-        wdt = torch.float64 if self.plan.problem.precision == 0 else torch.float32
+        wdt = self._wdt()
         if x.dtype != wdt or tuple(x.shape) != self.shape or not x.is_contiguous():
             raise ValueError(f"x must be contiguous {wdt} of shape {self.shape}")
         y = torch.empty_like(x)
@@ -87,7 +92,7 @@ class Solver:
         return y
 
     def time_solve(self, S: torch.Tensor, c_bar: float = 0.0) -> torch.Tensor:
-        wdt = torch.float64 if self.plan.problem.precision == 0 else torch.float32
+        wdt = self._wdt()
         if S.dtype != wdt or tuple(S.shape) != self.shape or not S.is_contiguous():
             raise ValueError(f"S must be contiguous {wdt} of shape {self.shape}")
         S = S.clone()

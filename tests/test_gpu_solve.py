@@ -26,7 +26,7 @@ def _run(p, u0, prec, **kw):
     return host(U), rep, s
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_c1_biharmonic_1d(prec):
     say(f"c1 {prec}")
     p = CONFIGS["c1"]
@@ -38,7 +38,7 @@ def test_c1_biharmonic_1d(prec):
     assert rep["status"] == 0 and err <= TOL
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_c2_linear_ch_2d_full_size(prec):
     say(f"c2 {prec}")
     p = CONFIGS["c2"]
@@ -60,10 +60,12 @@ SOLVE_CASES = [
     Problem(op="ch", dim=1, n=128, nt=128, dt=1e-5, eps=0.05, alpha=1e-3),
     Problem(op="ch_eyre", dim=2, n=32, nt=32, dt=1e-5, eps=0.05, alpha=1e-3),
     Problem(op="linear_ch", dim=2, n=128, nt=1024, dt=1e-6, eps=0.05, beta=0.5, alpha=1e-3),
+    Problem(op="ch", dim=2, n=256, nt=16, dt=1e-6, eps=0.01, alpha=1e-3),
+    Problem(op="linear_ch", dim=2, n=512, nt=8, dt=1e-6, eps=0.0075, beta=0.5, alpha=1e-3),
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 @pytest.mark.parametrize("p", SOLVE_CASES, ids=[f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}-th{p.theta}" for p in SOLVE_CASES])
 def test_solve_matches_oracle(p, prec):
     say(f"solve {prec} {p}")

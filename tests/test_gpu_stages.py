@@ -42,6 +42,9 @@ CASES = [
     Problem(op="ch", dim=2, n=64, nt=32, dt=1e-6, eps=0.02, alpha=0.01),
     Problem(op="ch_eyre", dim=2, n=32, nt=16, dt=1e-5, eps=0.05, alpha=0.05),
     Problem(op="linear_ch", dim=2, n=128, nt=16, dt=1e-5, eps=0.05, beta=0.5, alpha=0.05),
+    Problem(op="ch", dim=2, n=256, nt=8, dt=1e-6, eps=0.01, alpha=0.05),
+    Problem(op="linear_ch", dim=2, n=512, nt=4, dt=1e-6, theta=0.5, eps=0.03, beta=0.4, alpha=0.1),
+    Problem(op="biharmonic", dim=1, n=32, nt=1024, dt=1e-6, alpha=0.05),
 ]
 IDS = [f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}" for p in CASES]
 
@@ -100,7 +103,7 @@ def test_time_solve_stage(p, prec):
     assert err < tol, (err, tol)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 @pytest.mark.parametrize("p", CASES, ids=IDS)
 def test_precond_stage(p, prec):
     say(f"precond stage {prec} {p}")
