@@ -3,8 +3,9 @@
 These are the schemes whose solution the parallel-in-time iteration converges
 to.  Each step is a direct spatial solve with LAPACK banded Cholesky
 (``scipy.linalg.cholesky_banded`` / ``cho_solve_banded``); nonlinear steps
-iterate on the frozen SPD matrix to a 1e-14 relative increment.  No transform
-of any kind is used.
+iterate on the frozen SPD matrix to a 1e-14 relative increment.  No fast
+transform is used; ``ch_step_modal`` (single steps on grids too large to
+factor) inverts the frozen matrix with the explicit dense cosine matrix.
 
 Schemes
 -------
@@ -128,6 +129,45 @@ def ch_eyre(dim: int, n: int, nt: int, dt: float, u0: np.ndarray, eps: float,
     """Eyre's convex/concave split CH (Section 4.1, eq. fully-dis_CH_WR_Eyre with
     alpha = 0): u^3 implicit, the -u part explicit."""
     return _ch_steps(dim, n, nt, dt, u0, eps, "eyre", return_iters)
+
+
+def ch_step_modal(u_prev: np.ndarray, dt: float, eps: float, scheme: str = "implicit") -> np.ndarray:
+    """One CH step (eq. fully-dis_CH, or the Eyre scheme) from the 2D or 1D
+    level u_prev, for grids where a banded factorization is too large.
+
+    Same chord iteration as ``ch_implicit`` / ``ch_eyre`` (frozen matrix
+    J0 = I/dt + Lap_h + eps^2 Lap_h^2, resp. I/dt + eps^2 Lap_h^2, same 1e-14
+    stop), but J0 is inverted in the explicit orthonormal cosine basis:
+    J0 = Q^T diag(j) Q with Q = allatonce.dct2_matrix(N) applied along each
+    axis and j the eigenvalues from the Laplacian spectrum.  Pinned against the
+    banded-Cholesky steppers on small grids.
+    """
+    from .allatonce import dct2_matrix
+    u_prev = np.asarray(u_prev, dtype=np.float64)
+    dim = u_prev.ndim
+    n = u_prev.shape[-1]
+    h = 1.0 / n
+    q = dct2_matrix(n)
+    lam1 = ops.spectrum_1d(n, h)
+    lam = lam1 if dim == 1 else lam1[:, None] + lam1[None, :]
+    jdiag = 1.0 / dt + eps * eps * lam * lam + (lam if scheme == "implicit" else 0.0)
+
+    def fwd(x):
+        return q @ x if dim == 1 else q @ x @ q.T
+
+    def inv(x):
+        return q.T @ x if dim == 1 else q.T @ x @ q
+
+    lap = ops.laplacian(dim, n, h)
+    up = u_prev.reshape(-1)
+    u = up.copy()
+    for _ in range(NEWTON_MAXIT):
+        f = ch_residual(u, up, lap, dt, eps, scheme).reshape(u_prev.shape)
+        du = inv(fwd(f) / jdiag).reshape(-1)
+        u = u - du
+        if np.max(np.abs(du)) <= NEWTON_TOL * max(1.0, np.max(np.abs(u))):
+            return u.reshape(u_prev.shape)
+    raise RuntimeError("modal CH step: chord iteration did not converge")
 
 
 def sequential(problem, u0: np.ndarray) -> np.ndarray:

@@ -151,3 +151,14 @@ def test_residual_level_form_matches_kronecker():
     S = stepper.sequential(p, u0)
     r0 = aao.residual_linear(p, S, u0)
     assert np.max(np.abs(r0)) * p.dt < 1e-11
+
+
+@pytest.mark.parametrize("scheme", ["implicit", "eyre"])
+@pytest.mark.parametrize("dim,n", [(2, 16), (1, 32)])
+def test_modal_ch_step_equals_banded_step(scheme, dim, n):
+    rng = np.random.default_rng(31)
+    dt, eps = 1e-5, 0.03
+    u0 = rng.uniform(-0.6, 0.6, (n,) * dim)
+    ref = (stepper.ch_implicit if scheme == "implicit" else stepper.ch_eyre)(dim, n, 1, dt, u0, eps)[0]
+    got = stepper.ch_step_modal(u0, dt, eps, scheme)
+    assert np.max(np.abs(got - ref)) < 1e-13
