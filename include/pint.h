@@ -214,6 +214,68 @@ int pint_precond_apply(pint_plan* plan, const double* d_r, double* d_delta, doub
 int pint_diagnostics(pint_plan* plan, const double* d_U, double* d_mass, double* d_energy,
                      void* stream);
 
+/* ------------------------------------------------------------- serving ----
+ * A persistent request loop (one worker thread per server) for streams of
+ * solves of uneven size.  Requests are admitted first come, first served as
+ * soon as a slot (a HIP stream) is free and their whole device footprint
+ * (plan tables + u0 + U + workspace) fits in the caller's pool.  Active
+ * requests advance one outer iteration at a time on their own streams, so
+ * their work overlaps on the device; a request retires as soon as its own
+ * stop rule holds and its slot and memory go to the next one (continuous
+ * batching).  Iterations after the first replay one captured HIP graph per
+ * (slot, shape class) -- shape class = (dim, N, N_t, precision, flags) --
+ * re-targeted to each request with hipGraphExecUpdate.  Results do not depend
+ * on what else is running: every request's kernels read and write only its
+ * own memory, in a fixed order.
+ */
+#define PINT_SERVER_NO_GRAPHS 0x1u  /* launch every iteration without graphs */
+
+typedef struct pint_server pint_server;
+
+typedef struct pint_server_config {
+  size_t struct_size;   /* sizeof(pint_server_config)                           */
+  void* d_pool;         /* caller-owned device memory, 256-byte aligned; the
+                           server sub-allocates every request's state from it   */
+  size_t pool_bytes;    /* >= 4096                                              */
+  int max_active;       /* requests in flight at once (HIP streams); 1..64, 0 = 8 */
+  unsigned flags;       /* PINT_SERVER_*                                        */
+} pint_server_config;
+
+typedef struct pint_server_statistics {
+  size_t struct_size;      /* sizeof(pint_server_statistics), set by caller    */
+  uint64_t submitted, completed, failed, cancelled;
+  int queued, active;
+  size_t pool_bytes, pool_in_use, pool_peak;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit-to-completion latency of
+                                              completed requests             */
+  double dof_completed;    /* sum of N_s * N_t over completed requests         */
+  double busy_seconds;     /* first admission to last completion               */
+  uint64_t graphs_captured, graph_updates, graph_launches;
+} pint_server_statistics;
+
+/* Start a server on the current device; *out receives it.  The pool stays
+ * owned by the caller and must outlive the server. */
+int pint_server_create(const pint_server_config* cfg, pint_server** out);
+/* Validate and enqueue one solve (u0 broadcast as the initial guess);
+ * h_u0 ([N_y][N_x] FP64 host) is copied, so the caller may reuse it at once.
+ * PINT_EINVAL for an invalid problem, PINT_ENOMEM if its footprint exceeds
+ * the whole pool.  *ticket identifies the request. */
+int pint_server_submit(pint_server* s, const pint_problem* p, const double* h_u0, uint64_t* ticket);
+/* Block until the request is done (timeout_ms < 0: no limit), copy U
+ * ([N_t][N_y][N_x] FP64 host, caller-owned) and the report, and release the
+ * ticket.  Returns the request's status (PINT_OK, PINT_ENOCONV, PINT_EDIVERGED,
+ * PINT_ECANCELED, ...), PINT_ETIMEDOUT (ticket kept) or PINT_ENOTFOUND. */
+int pint_server_wait(pint_server* s, uint64_t ticket, double* h_U, pint_report* rep, int timeout_ms);
+/* Cancel a queued or running request (it completes with PINT_ECANCELED). */
+int pint_server_cancel(pint_server* s, uint64_t ticket);
+/* Snapshot of the counters and latency percentiles. */
+int pint_server_stats(pint_server* s, pint_server_statistics* st);
+/* Cancel queued requests, finish running ones, stop the worker, free the
+ * server's streams and host buffers.  NULL is accepted. */
+int pint_server_destroy(pint_server* s);
+/* Message of the last failing server call ("" if none). */
+const char* pint_server_last_error(const pint_server* s);
+
 #ifdef __cplusplus
 }
 #endif

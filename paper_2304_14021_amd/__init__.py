@@ -6,3 +6,4 @@ this package only marshals arguments to it.
 """
 from ._pint import PintError, lib  # noqa: F401
 from .solver import Solver  # noqa: F401
+from .server import Server  # noqa: F401

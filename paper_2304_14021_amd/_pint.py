@@ -31,7 +31,10 @@ EXPORTS = (
     "pint_plan_create", "pint_plan_destroy", "pint_plan_last_error", "pint_plan_workspace_size",
     "pint_plan_alpha", "pint_solve", "pint_residual", "pint_dct", "pint_time_solve",
     "pint_precond_apply", "pint_diagnostics",
+    "pint_server_create", "pint_server_submit", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
+    "pint_server_destroy", "pint_server_last_error",
 )
+SERVER_NO_GRAPHS = 0x1
 
 
 class Problem(ct.Structure):
@@ -53,6 +56,25 @@ class Report(ct.Structure):
         ("alpha_used", ct.c_double), ("c_bar", ct.c_double), ("est_rel_err", ct.c_double),
         ("res_hist", ct.c_double * HIST), ("upd_hist", ct.c_double * HIST),
         ("ms_stage", ct.c_double * 8), ("ms_total", ct.c_double),
+    ]
+
+
+class ServerConfig(ct.Structure):
+    _fields_ = [
+        ("struct_size", ct.c_size_t), ("d_pool", ct.c_void_p), ("pool_bytes", ct.c_size_t),
+        ("max_active", ct.c_int), ("flags", ct.c_uint),
+    ]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [
+        ("struct_size", ct.c_size_t),
+        ("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("failed", ct.c_uint64), ("cancelled", ct.c_uint64),
+        ("queued", ct.c_int), ("active", ct.c_int),
+        ("pool_bytes", ct.c_size_t), ("pool_in_use", ct.c_size_t), ("pool_peak", ct.c_size_t),
+        ("p50_ms", ct.c_double), ("p99_ms", ct.c_double), ("mean_ms", ct.c_double), ("max_ms", ct.c_double),
+        ("dof_completed", ct.c_double), ("busy_seconds", ct.c_double),
+        ("graphs_captured", ct.c_uint64), ("graph_updates", ct.c_uint64), ("graph_launches", ct.c_uint64),
     ]
 
 
@@ -90,8 +112,17 @@ class Lib:
         d.pint_time_solve.argtypes = [vp, vp, dbl, vp]
         d.pint_precond_apply.argtypes = [vp, vp, vp, dbl, vp, sz, vp]
         d.pint_diagnostics.argtypes = [vp, vp, vp, vp, vp]
+        d.pint_server_create.argtypes = [ct.POINTER(ServerConfig), ct.POINTER(vp)]
+        d.pint_server_submit.argtypes = [vp, ct.POINTER(Problem), vp, ct.POINTER(ct.c_uint64)]
+        d.pint_server_wait.argtypes = [vp, ct.c_uint64, vp, ct.POINTER(Report), i]
+        d.pint_server_cancel.argtypes = [vp, ct.c_uint64]
+        d.pint_server_stats.argtypes = [vp, ct.POINTER(ServerStats)]
+        d.pint_server_destroy.argtypes = [vp]
+        d.pint_server_last_error.restype = ct.c_char_p
+        d.pint_server_last_error.argtypes = [vp]
         for name in EXPORTS:
-            if name not in ("pint_status_string", "pint_last_error", "pint_version", "pint_plan_last_error"):
+            if name not in ("pint_status_string", "pint_last_error", "pint_version", "pint_plan_last_error",
+                            "pint_server_last_error"):
                 getattr(d, name).restype = ct.c_int
 
     def check(self, rc: int, plan=None, ok=(PINT_OK,)):

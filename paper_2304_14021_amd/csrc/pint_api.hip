@@ -16,6 +16,7 @@
 
 #include "pint.h"
 #include "pint_kernels.hpp"
+#include "pint_internal.hpp"
 
 using namespace pint;
 
@@ -49,7 +50,10 @@ struct pint_plan {
 
   // device tables (one allocation), FP64 then FP32 copies
   void* d_tab = nullptr;
+  bool own_tab = true;
   size_t tab_bytes = 0;
+  std::vector<unsigned char> host_tab;  // kept alive for asynchronous table copies
+  size_t offs_d[11] = {}, offs_f[11] = {};  // table offsets (FP64 / FP32 copies) in the block
   DctTables<double> dtd{};
   DctTables<float> dtf{};
   TimeArgs<double> tad{};
@@ -60,7 +64,7 @@ struct pint_plan {
   std::vector<hipEvent_t> ev;
 
   ~pint_plan() {
-    if (d_tab) (void)hipFree(d_tab);
+    if (d_tab && own_tab) (void)hipFree(d_tab);
     if (h_ctrl) (void)hipHostFree(h_ctrl);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -225,6 +229,12 @@ Offs put_all(std::vector<unsigned char>& buf, const HostTables& t) {
   return o;
 }
 
+void store_offs(const Offs& o, size_t* dst) {
+  const size_t v[11] = {o.tw_s, o.wq, o.wi, o.tw_t, o.lam1, o.pco, o.qco, o.aj, o.aij, o.lamx, o.lamy};
+  for (int i = 0; i < 11; ++i) dst[i] = v[i];
+}
+Offs load_offs(const size_t* s) { return Offs{s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8], s[9], s[10]}; }
+
 template <typename T>
 void bind(const Offs& o, unsigned char* base, const pint_plan* pl, DctTables<T>& dt, TimeArgs<T>& ta) {
   dt.tw = reinterpret_cast<const cx<T>*>(base + o.tw_s);
@@ -316,7 +326,7 @@ TimeArgs<float> time_args<float>(const pint_plan* pl) { return pl->taf; }
 // datum u0 (first iteration).
 template <typename TF, typename T>
 int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st,
-                      hipEvent_t* evs, bool bcast) {
+                      hipEvent_t* evs, bool bcast, Ctrl* host) {
   TimeArgs<T> ta = time_args<T>(pl);
   ta.cbar = &w.ctrl->c_bar;
   ta.done = &w.ctrl->done;
@@ -326,7 +336,7 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.part = w.part;
   ra.done = &w.ctrl->done;
   ra.bcast = bcast ? 1 : 0;
-  FinArgs fa{w.ctrl, pl->h_ctrl, w.part, pl->nt, pl->nbl, pl->max_iter, pl->dof, pl->rtol, pl->safety};
+  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->dof, pl->rtol, pl->safety};
   UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0};
   T* S = static_cast<T*>(w.S);
   TF* SF = std::is_same<TF, T>::value ? reinterpret_cast<TF*>(w.S) : static_cast<TF*>(w.S64);
@@ -357,10 +367,31 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
 }
 
 int enqueue_any(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st, hipEvent_t* evs,
-                bool bcast) {
-  if (pl->fp64) return enqueue_iteration<double, double>(pl, d_u0, d_U, w, st, evs, bcast);
-  if (pl->mixed) return enqueue_iteration<double, float>(pl, d_u0, d_U, w, st, evs, bcast);
-  return enqueue_iteration<float, float>(pl, d_u0, d_U, w, st, evs, bcast);
+                bool bcast, Ctrl* host) {
+  if (pl->fp64) return enqueue_iteration<double, double>(pl, d_u0, d_U, w, st, evs, bcast, host);
+  if (pl->mixed) return enqueue_iteration<double, float>(pl, d_u0, d_U, w, st, evs, bcast, host);
+  return enqueue_iteration<float, float>(pl, d_u0, d_U, w, st, evs, bcast, host);
+}
+
+int begin_solve(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st, Ctrl* host) {
+  const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
+  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, pl->nbl, bcast ? 1 : 0};
+  const bool need_cbar = pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE;
+  HIPCHK(launch_init(ia, w.ctrl, host, pl->dof, need_cbar, st), "init kernels");
+  return PINT_OK;
+}
+
+void fill_report(const pint_plan* pl, const Ctrl& c, int status, pint_report* rep) {
+  std::memset(reinterpret_cast<char*>(rep) + sizeof(size_t), 0, sizeof(pint_report) - sizeof(size_t));
+  rep->status = status;
+  rep->iterations = c.iter;
+  rep->alpha_used = pl->alpha;
+  rep->c_bar = c.c_bar;
+  rep->est_rel_err = c.est;
+  for (int k = 0; k < PINT_HIST && k < c.iter; ++k) {
+    rep->upd_hist[k] = c.upd_hist[k];
+    rep->res_hist[k] = c.res_hist[k];
+  }
 }
 
 }  // namespace
@@ -386,7 +417,13 @@ const char* pint_status_string(int s) {
 const char* pint_last_error(void) { return g_last_error.c_str(); }
 const char* pint_version(void) { return "pint-mi355x 0.1 (gfx950)"; }
 
-int pint_plan_create(const pint_problem* p, pint_plan** out) {
+int pint_plan_create(const pint_problem* p, pint_plan** out) { return pint::plan_create_ex(p, pint::PlanOpts{}, out); }
+
+}  // extern "C"
+
+namespace pint {
+
+int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out) {
   if (!out) return set_err(nullptr, PINT_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate(p, nullptr);
@@ -456,34 +493,114 @@ int pint_plan_create(const pint_problem* p, pint_plan** out) {
 
   HostTables t;
   build_tables(pl, t);
-  std::vector<unsigned char> buf;
-  Offs od = put_all<double>(buf, t);
-  Offs of = put_all<float>(buf, t);
+  std::vector<unsigned char>& buf = pl->host_tab;
+  store_offs(put_all<double>(buf, t), pl->offs_d);
+  store_offs(put_all<float>(buf, t), pl->offs_f);
   pl->tab_bytes = align256(buf.size());
-  hipError_t e = hipMalloc(&pl->d_tab, pl->tab_bytes);
-  if (e != hipSuccess) {
-    rc = hip_fail(nullptr, e, "hipMalloc(tables)");
-    delete pl;
-    return rc;
+  if (!opts.defer_tables) {
+    void* mem = opts.d_tables;
+    if (!mem) {
+      hipError_t e = hipMalloc(&mem, pl->tab_bytes);
+      if (e != hipSuccess) {
+        rc = hip_fail(nullptr, e, "hipMalloc(tables)");
+        delete pl;
+        return rc;
+      }
+      pl->d_tab = mem;  // owned
+      e = hipMemcpy(mem, buf.data(), buf.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        rc = hip_fail(nullptr, e, "table copy");
+        delete pl;
+        return rc;
+      }
+      plan_bind_tables(pl, mem, nullptr, false);
+    } else {
+      rc = plan_bind_tables(pl, mem, opts.stream, true);
+      if (rc) {
+        delete pl;
+        return rc;
+      }
+    }
   }
-  e = hipMemcpy(pl->d_tab, buf.data(), buf.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    rc = hip_fail(nullptr, e, "hipMemcpy(tables)");
-    delete pl;
-    return rc;
-  }
-  unsigned char* base = static_cast<unsigned char*>(pl->d_tab);
-  bind<double>(od, base, pl, pl->dtd, pl->tad);
-  bind<float>(of, base, pl, pl->dtf, pl->taf);
-  e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_ctrl), sizeof(Ctrl), hipHostMallocCoherent);
-  if (e != hipSuccess) {
-    rc = hip_fail(nullptr, e, "hipHostMalloc(status mirror)");
-    delete pl;
-    return rc;
+  if (opts.host_mirror) {
+    const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&pl->h_ctrl), sizeof(Ctrl), hipHostMallocCoherent);
+    if (e != hipSuccess) {
+      rc = hip_fail(nullptr, e, "hipHostMalloc(status mirror)");
+      delete pl;
+      return rc;
+    }
   }
   *out = pl;
   return PINT_OK;
 }
+
+int plan_bind_tables(pint_plan* pl, void* d_mem, hipStream_t st, bool copy) {
+  if (pl->d_tab && pl->own_tab && pl->d_tab != d_mem) (void)hipFree(pl->d_tab);
+  pl->d_tab = d_mem;
+  pl->own_tab = !copy;  // a copied-into block belongs to the caller
+  if (copy) {
+    hipError_t e = hipMemcpyAsync(d_mem, pl->host_tab.data(), pl->host_tab.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(pl, e, "table copy");
+  }
+  unsigned char* base = static_cast<unsigned char*>(d_mem);
+  bind<double>(load_offs(pl->offs_d), base, pl, pl->dtd, pl->tad);
+  bind<float>(load_offs(pl->offs_f), base, pl, pl->dtf, pl->taf);
+  return PINT_OK;
+}
+
+size_t plan_table_bytes(const pint_problem* p) {
+  // the table block depends only on N and N_t
+  HostTables t;
+  t.tw_s.resize(p->nx);
+  t.wq.resize(p->nx);
+  t.wi.resize(p->nx);
+  t.tw_t.resize(p->nt);
+  t.lam1.resize(p->nt);
+  t.pco.resize(p->nt);
+  t.qco.resize(p->nt);
+  t.aj.resize(p->nt);
+  t.aij.resize(p->nt);
+  t.lamx.resize(p->nx);
+  t.lamy.resize(p->dim == 2 ? p->nx : 1);
+  std::vector<unsigned char> buf;
+  put_all<double>(buf, t);
+  put_all<float>(buf, t);
+  return align256(buf.size());
+}
+
+size_t plan_workspace_bytes(const pint_plan* pl) { return work_size(pl); }
+int plan_max_iter(const pint_plan* pl) { return pl->max_iter; }
+int plan_nt(const pint_plan* pl) { return pl->nt; }
+int plan_ns(const pint_plan* pl) { return pl->ns; }
+
+int solve_begin(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, size_t work_bytes, hipStream_t st,
+                Ctrl* host) {
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  return begin_solve(pl, d_u0, d_U, w, st, host);
+}
+
+int solve_enqueue(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, size_t work_bytes, hipStream_t st,
+                  Ctrl* host, int it) {
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
+  return enqueue_any(pl, d_u0, d_U, w, st, nullptr, bcast && it == 0, host);
+}
+
+int solve_status(const pint_plan* pl, const Ctrl& c, pint_report* rep) {
+  const int status = c.done ? c.status : PINT_ENOCONV;
+  if (rep) fill_report(pl, c, status, rep);
+  return status;
+}
+
+}  // namespace pint
+
+extern "C" {
+
+
 
 int pint_plan_destroy(pint_plan* plan) {
   delete plan;
@@ -524,9 +641,8 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
     }
   }
   const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
-  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, pl->nbl, bcast ? 1 : 0};
-  const bool need_cbar = pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE;
-  HIPCHK(launch_init(ia, w.ctrl, pl->h_ctrl, pl->dof, need_cbar, st), "init kernels");
+  rc = begin_solve(pl, d_u0, d_U, w, st, pl->h_ctrl);
+  if (rc) return rc;
   // Enqueue as many iterations as the previous solve of this plan needed
   // (kernels after the device stop flag is set return at once), then check
   // the flag after each further iteration.
@@ -534,7 +650,7 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
   const int first_check = std::min(std::max(pl->predict, 2), pl->max_iter);
   for (; it < pl->max_iter; ++it) {
     hipEvent_t* evs = timing ? &pl->ev[EV_PER_IT * it] : nullptr;
-    rc = enqueue_any(pl, d_u0, d_U, w, st, evs, bcast && it == 0);
+    rc = enqueue_any(pl, d_u0, d_U, w, st, evs, bcast && it == 0, pl->h_ctrl);
     if (rc) return rc;
     if (it + 1 >= first_check) {
       HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -549,16 +665,7 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
   const int status = c.done ? c.status : PINT_ENOCONV;
   if (status == PINT_OK) pl->predict = c.iter;
   if (rep) {
-    std::memset(reinterpret_cast<char*>(rep) + sizeof(size_t), 0, sizeof(pint_report) - sizeof(size_t));
-    rep->status = status;
-    rep->iterations = c.iter;
-    rep->alpha_used = pl->alpha;
-    rep->c_bar = c.c_bar;
-    rep->est_rel_err = c.est;
-    for (int k = 0; k < PINT_HIST && k < c.iter; ++k) {
-      rep->upd_hist[k] = c.upd_hist[k];
-      rep->res_hist[k] = c.res_hist[k];
-    }
+    fill_report(pl, c, status, rep);
     if (timing) {
       for (int k = 0; k < c.iter && k < it; ++k)
         for (int s = 0; s < EV_PER_IT - 1; ++s) {
