@@ -98,6 +98,131 @@ def cpu_baseline(name: str, min_seconds: float = 10.0):
     }
 
 
+SERVED = ("c4: 512 Poisson-arrival requests, biharmonic heat / linearized CH 50/50, grids {64^2,128^2,256^2}, "
+          "levels {32,64,128}, eps ~ U[0.02,0.08], beta ~ U[0,0.57], dt=1e-5, u0 ~ U[-0.05,0.05] (seed 4)")
+
+
+def _spin_until(t_target):
+    while True:
+        d = t_target - time.perf_counter()
+        if d <= 0:
+            return
+        if d > 2e-3:
+            time.sleep(d - 1e-3)
+
+
+def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, graphs=True):
+    """The served stream through the library's serving loop.
+
+    Closed loop: all requests queued at once; the saturation rate is requests
+    (and DOF) per second from the first submission to the last completion.
+    Open loop: Poisson arrivals at 0.5x and 0.9x that rate, each request
+    submitted at its arrival time; latency = completion - scheduled arrival.
+    Device-resident requests (u0 and U in HBM, no host copies) unless
+    stated; the host-buffer variant is measured once for the PCIe-inclusive
+    rate."""
+    import numpy as np
+    import torch
+    from oracle import stepper
+    from paper_2304_14021_amd import Server, Solver
+    from workloads import request_u0, served_stream
+
+    reqs = served_stream(n_requests=n_requests, seed=4, rate=1.0)
+    u0h = [request_u0(r) for r in reqs]
+    u0d = [torch.from_numpy(u).to(dev) for u in u0h]
+    Ud = [torch.empty(r.problem.shape, dtype=torch.float64, device=dev) for r in reqs]
+    dof = np.array([r.problem.dof for r in reqs], dtype=np.float64)
+    base_arr = np.array([r.arrival for r in reqs])
+    torch.cuda.synchronize()
+    pool = int(pool_gib * (1 << 30))
+
+    def run(srv, rate, host_io=False):
+        """rate None: closed loop.  Returns (wall s, latencies ms, reports)."""
+        sched = None if rate is None else base_arr / rate
+        h0 = srv.stats()["worker_host_seconds"]
+        tickets, t_sub = [], []
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if sched is not None:
+                _spin_until(t0 + sched[i])
+            t_sub.append(time.perf_counter())
+            if host_io:
+                tickets.append(srv.submit(r.problem, u0h[i], precision=precision))
+            else:
+                tickets.append(srv.submit_device(r.problem, u0d[i], Ud[i], precision=precision, sync=False))
+        t_subs_done = time.perf_counter() - t0
+        reps = [srv.wait(t)[1] for t in tickets]
+        wall = time.perf_counter() - t0
+        for rp in reps:
+            rp["_worker_s"] = srv.stats()["worker_host_seconds"] - h0
+            rp["_submit_s"] = t_subs_done
+            break
+        ts = np.array(t_sub) - t0
+        late = ts - (sched if sched is not None else ts)
+        lat = np.array([rp["ms_total"] for rp in reps]) + late * 1e3
+        return wall, lat, reps
+
+    def summary(wall, lat, reps, rate=None):
+        its = [rp["iterations"] for rp in reps]
+        bad = sum(rp["status"] != 0 for rp in reps)
+        d = {"requests": len(reps), "failed": int(bad), "wall_s": wall, "req_per_s": len(reps) / wall,
+             "dof_per_s": float(dof.sum()) / wall, "p50_ms": float(np.percentile(lat, 50)),
+             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+             "iterations_mean": float(np.mean(its)), "submit_loop_s": reps[0]["_submit_s"],
+             "worker_host_s": reps[0]["_worker_s"]}
+        if rate is not None:
+            d["arrival_rate_req_per_s"] = rate
+        return d
+
+    out = {"workload": SERVED, "precision": PREC_DESC[precision], "slots": slots, "pool_bytes": pool,
+           "graphs": graphs,
+           "io": "device-resident (u0 and U in HBM)"}
+    with Server(pool, max_active=slots, graphs=graphs, device=dev) as srv:
+        run(srv, None)  # warm-up: captures every (slot, shape class) graph once
+        w, lat, reps = run(srv, None)
+        sat = summary(w, lat, reps)
+        out["saturation"] = sat
+        log(f"serving saturation: {json.dumps(sat)}")
+        for f in (0.5, 0.9):
+            rate = f * sat["req_per_s"]
+            w, lat, reps = run(srv, rate)
+            out[f"load_{f}"] = summary(w, lat, reps, rate)
+            log(f"serving at {f} x saturation: {json.dumps(out[f'load_{f}'])}")
+        st = srv.stats()
+        out["server_stats"] = {k: st[k] for k in ("graphs_captured", "graph_updates", "graph_launches",
+                                                  "pool_peak", "failed")}
+        # PCIe-inclusive: u0 from and U back to host memory, closed loop
+        run(srv, None, host_io=True)
+        w, lat, reps = run(srv, None, host_io=True)
+        out["host_io_saturation"] = summary(w, lat, reps)
+    # one request at a time, each timed alone (plan and workspace made
+    # beforehand, not timed): what the same stream costs without batching
+    solo = 0.0
+    for i, r in enumerate(reqs):
+        s = Solver.for_problem(r.problem, precision=precision, device=dev)
+        s.solve(u0d[i], Ud[i])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        s.solve(u0d[i], Ud[i])
+        torch.cuda.synchronize()
+        solo += time.perf_counter() - ts
+        del s
+    out["one_at_a_time"] = {"dof_per_s": float(dof.sum()) / solo, "req_per_s": len(reqs) / solo,
+                            "note": "sum of standalone solve times of the same requests"}
+    # served results (last device-resident pass) against the oracle, on the
+    # smallest requests
+    errs = []
+    with Server(pool, max_active=slots, device=dev) as srv:
+        order = np.argsort(dof)[:oracle_checks]
+        tk = [(i, srv.submit_device(reqs[i].problem, u0d[i], Ud[i], precision=precision)) for i in order]
+        for i, t in tk:
+            srv.wait(t)
+            errs.append(stepper.rel_err(Ud[i].cpu().numpy(), stepper.sequential(reqs[i].problem, u0h[i])))
+    out["rel_err_vs_oracle_max"] = float(max(errs)) if errs else None
+    out["oracle_checked_requests"] = len(errs)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +232,11 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-pool-gib", type=float, default=8.0)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-no-graphs", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device-to-device copy launched before the steps (counter calibration)")
     args = ap.parse_args()
@@ -228,6 +358,9 @@ def main():
             out["paths"][other] = {"value": p.dof * args.steps / elo, "ms_per_step": elo / args.steps * 1e3,
                                    "iterations": repso[-1]["iterations"],
                                    "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref)}
+    if not args.no_serving:
+        out["serving"] = serving_bench(dev, args.precision, args.serve_slots, args.serve_pool_gib,
+                                       args.serve_requests, oracle_checks=8, graphs=not args.serve_no_graphs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)

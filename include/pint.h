@@ -251,20 +251,38 @@ typedef struct pint_server_statistics {
   double dof_completed;    /* sum of N_s * N_t over completed requests         */
   double busy_seconds;     /* first admission to last completion               */
   uint64_t graphs_captured, graph_updates, graph_launches;
+  double worker_host_seconds;  /* worker thread time spent admitting requests and
+                                  enqueueing their iterations                  */
 } pint_server_statistics;
 
 /* Start a server on the current device; *out receives it.  The pool stays
- * owned by the caller and must outlive the server. */
+ * owned by the caller and must outlive the server.  A finished request
+ * submitted with host buffers keeps its block of the pool (its U stays in
+ * HBM) until pint_server_wait copies U out, so results that are never
+ * collected keep their memory until the server is destroyed. */
 int pint_server_create(const pint_server_config* cfg, pint_server** out);
 /* Validate and enqueue one solve (u0 broadcast as the initial guess);
  * h_u0 ([N_y][N_x] FP64 host) is copied, so the caller may reuse it at once.
  * PINT_EINVAL for an invalid problem, PINT_ENOMEM if its footprint exceeds
  * the whole pool.  *ticket identifies the request. */
 int pint_server_submit(pint_server* s, const pint_problem* p, const double* h_u0, uint64_t* ticket);
+/* Device-resident variant: the solve reads d_u0 ([N_y][N_x] FP64) and
+ * iterates in place on d_U ([N_t][N_y][N_x] FP64), both caller-owned device
+ * memory on the server's device, 8-byte aligned and not overlapping.  No
+ * host copy is made in either direction and only the plan tables and the
+ * workspace come from the pool.  d_u0 must hold its final values when this is
+ * called (synchronize the stream that wrote it first); both buffers must stay
+ * allocated and untouched until pint_server_wait has returned for the ticket,
+ * after which d_U holds the result, visible to work on any stream.
+ * pint_server_wait ignores h_U for such requests.  Errors as for
+ * pint_server_submit, and PINT_EINVAL for NULL or misaligned buffers. */
+int pint_server_submit_device(pint_server* s, const pint_problem* p, const double* d_u0, double* d_U,
+                              uint64_t* ticket);
 /* Block until the request is done (timeout_ms < 0: no limit), copy U
- * ([N_t][N_y][N_x] FP64 host, caller-owned) and the report, and release the
- * ticket.  Returns the request's status (PINT_OK, PINT_ENOCONV, PINT_EDIVERGED,
- * PINT_ECANCELED, ...), PINT_ETIMEDOUT (ticket kept) or PINT_ENOTFOUND. */
+ * ([N_t][N_y][N_x] FP64 host, caller-owned; may be NULL) and the report, and
+ * release the ticket.  Returns the request's status (PINT_OK, PINT_ENOCONV, PINT_EDIVERGED,
+ * PINT_ECANCELED, ...), PINT_ETIMEDOUT (ticket kept), PINT_ENOTFOUND, or
+ * PINT_EINVAL if another thread is already waiting for the same ticket. */
 int pint_server_wait(pint_server* s, uint64_t ticket, double* h_U, pint_report* rep, int timeout_ms);
 /* Cancel a queued or running request (it completes with PINT_ECANCELED). */
 int pint_server_cancel(pint_server* s, uint64_t ticket);
@@ -273,7 +291,9 @@ int pint_server_stats(pint_server* s, pint_server_statistics* st);
 /* Cancel queued requests, finish running ones, stop the worker, free the
  * server's streams and host buffers.  NULL is accepted. */
 int pint_server_destroy(pint_server* s);
-/* Message of the last failing server call ("" if none). */
+/* Message of the last failing server call made by the calling thread ("" if
+ * none); for a request that failed on the device side, its message becomes the
+ * error of the thread whose pint_server_wait returned that failure. */
 const char* pint_server_last_error(const pint_server* s);
 
 #ifdef __cplusplus

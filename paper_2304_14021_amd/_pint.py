@@ -31,7 +31,7 @@ EXPORTS = (
     "pint_plan_create", "pint_plan_destroy", "pint_plan_last_error", "pint_plan_workspace_size",
     "pint_plan_alpha", "pint_solve", "pint_residual", "pint_dct", "pint_time_solve",
     "pint_precond_apply", "pint_diagnostics",
-    "pint_server_create", "pint_server_submit", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
+    "pint_server_create", "pint_server_submit", "pint_server_submit_device", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
     "pint_server_destroy", "pint_server_last_error",
 )
 SERVER_NO_GRAPHS = 0x1
@@ -75,6 +75,7 @@ class ServerStats(ct.Structure):
         ("p50_ms", ct.c_double), ("p99_ms", ct.c_double), ("mean_ms", ct.c_double), ("max_ms", ct.c_double),
         ("dof_completed", ct.c_double), ("busy_seconds", ct.c_double),
         ("graphs_captured", ct.c_uint64), ("graph_updates", ct.c_uint64), ("graph_launches", ct.c_uint64),
+        ("worker_host_seconds", ct.c_double),
     ]
 
 
@@ -114,6 +115,7 @@ class Lib:
         d.pint_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         d.pint_server_create.argtypes = [ct.POINTER(ServerConfig), ct.POINTER(vp)]
         d.pint_server_submit.argtypes = [vp, ct.POINTER(Problem), vp, ct.POINTER(ct.c_uint64)]
+        d.pint_server_submit_device.argtypes = [vp, ct.POINTER(Problem), vp, vp, ct.POINTER(ct.c_uint64)]
         d.pint_server_wait.argtypes = [vp, ct.c_uint64, vp, ct.POINTER(Report), i]
         d.pint_server_cancel.argtypes = [vp, ct.c_uint64]
         d.pint_server_stats.argtypes = [vp, ct.POINTER(ServerStats)]

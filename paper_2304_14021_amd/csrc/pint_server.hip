@@ -43,18 +43,23 @@ struct Req {
   pint_problem prob{};
   pint_plan* plan = nullptr;
   std::vector<double> u0;
-  std::vector<double> result;
+  bool held = false;             // finished; U still in the pool block for wait
+  double* d_res = nullptr;       // where (pool block of a host-buffer request)
+  const double* d_u0 = nullptr;  // caller-owned device input (device-resident requests)
+  double* d_U = nullptr;         // caller-owned device state and result
   pint_report rep{};
   int status = PINT_OK;
+  std::string err;  // message of a worker-side failure
   ReqState state = RQ_QUEUED;
   bool cancel = false;
+  bool waited = false;  // a pint_server_wait call holds this ticket
   size_t ns = 0, nt = 0;
   size_t tab_bytes = 0, work_bytes = 0, footprint = 0;
   size_t pool_off = 0;
   Clock::time_point t_submit, t_admit, t_done;
 };
 
-enum SlotState { SL_IDLE, SL_RUNNING, SL_DRAINING };
+enum SlotState { SL_IDLE, SL_RUNNING };
 
 using ShapeKey = std::tuple<int, int, int, int, unsigned>;  // dim, n, nt, precision, flags
 
@@ -63,8 +68,7 @@ struct Slot {
   hipEvent_t ev = nullptr;
   Ctrl* h_ctrl = nullptr;  // pinned status mirror of the running request
   double* h_in = nullptr;  // pinned staging for u0
-  double* h_out = nullptr; // pinned staging for U
-  size_t in_cap = 0, out_cap = 0;
+  size_t in_cap = 0;
   SlotState state = SL_IDLE;
   Req* req = nullptr;
   int it_enq = 0;
@@ -137,7 +141,6 @@ struct pint_server {
   std::condition_variable cv_work, cv_done;
   bool stop = false;
   std::thread worker;
-  std::string err;
   std::map<ShapeKey, int> predict;  // iterations the last request of a shape class needed
   // statistics
   uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
@@ -145,6 +148,7 @@ struct pint_server {
   size_t pool_peak = 0;
   std::vector<double> lat_ms;
   double dof_done = 0.0;
+  double host_seconds = 0.0;  // worker time spent admitting and advancing requests
   bool have_first = false;
   Clock::time_point t_first, t_last;
   int fatal = PINT_OK;
@@ -154,9 +158,10 @@ namespace {
 
 thread_local std::string g_srv_err;
 
-int srv_fail(pint_server* s, int code, const std::string& msg) {
+// Errors are per calling thread; a request's worker-side error travels with
+// the request and becomes the waiting thread's error.
+int srv_fail(pint_server*, int code, const std::string& msg) {
   g_srv_err = msg;
-  if (s) s->err = msg;
   return code;
 }
 
@@ -164,6 +169,11 @@ ShapeKey key_of(const pint_problem& p) { return ShapeKey(p.dim, p.nx, p.nt, p.pr
 
 void finish_req(pint_server* s, Req* r, int status) {
   r->status = status;
+  if (status != PINT_OK && status != PINT_ECANCELED && status != PINT_ENOCONV && status != PINT_EDIVERGED) {
+    // the failing worker-side call left its message on the plan or here
+    const char* pe = r->plan ? pint_plan_last_error(r->plan) : nullptr;
+    r->err = (pe && *pe) ? std::string(pe) : g_srv_err;
+  }
   r->state = RQ_DONE;
   r->t_done = Clock::now();
   if (r->plan) {
@@ -252,13 +262,22 @@ int start_req(pint_server* s, Slot& sl, Req* r) {
   sl.d_U = reinterpret_cast<double*>(base);
   base += al256(r->ns * r->nt * sizeof(double));
   sl.d_work = base;
-  if (!grow_pinned(&sl.h_in, &sl.in_cap, r->ns) || !grow_pinned(&sl.h_out, &sl.out_cap, r->ns * r->nt))
-    return srv_fail(s, PINT_ENOMEM, "pinned staging allocation failed");
-  int rc = plan_bind_tables(r->plan, d_tab, sl.st, true);
-  if (rc) return rc;
-  std::memcpy(sl.h_in, r->u0.data(), r->ns * sizeof(double));
-  if (hipMemcpyAsync(sl.d_u0, sl.h_in, r->ns * sizeof(double), hipMemcpyHostToDevice, sl.st) != hipSuccess)
-    return srv_fail(s, PINT_EHIP, "u0 copy failed");
+  int rc = PINT_OK;
+  if (r->d_U) {
+    sl.d_work = sl.d_u0;  // no u0/U in the pool: the workspace follows the tables
+    sl.d_u0 = const_cast<double*>(r->d_u0);
+    sl.d_U = r->d_U;
+    rc = plan_bind_tables(r->plan, d_tab, sl.st, true);
+    if (rc) return rc;
+  } else {
+    if (!grow_pinned(&sl.h_in, &sl.in_cap, r->ns))
+      return srv_fail(s, PINT_ENOMEM, "pinned staging allocation failed");
+    rc = plan_bind_tables(r->plan, d_tab, sl.st, true);
+    if (rc) return rc;
+    std::memcpy(sl.h_in, r->u0.data(), r->ns * sizeof(double));
+    if (hipMemcpyAsync(sl.d_u0, sl.h_in, r->ns * sizeof(double), hipMemcpyHostToDevice, sl.st) != hipSuccess)
+      return srv_fail(s, PINT_EHIP, "u0 copy failed");
+  }
   rc = solve_begin(r->plan, sl.d_u0, sl.d_U, sl.d_work, r->work_bytes, sl.st, sl.h_ctrl);
   if (rc) return rc;
   sl.req = r;
@@ -284,40 +303,36 @@ int start_req(pint_server* s, Slot& sl, Req* r) {
   return PINT_OK;
 }
 
-// Advance a slot whose last event completed.  Lock held.
+// Advance a slot whose last event completed: retire its request if it has
+// stopped, else enqueue one more iteration.  Lock held.  A retired
+// host-buffer request keeps its pool block (U stays in HBM) until
+// pint_server_wait copies U out on the caller's thread.
 int advance(pint_server* s, Slot& sl) {
   Req* r = sl.req;
-  if (sl.state == SL_RUNNING) {
-    const Ctrl& c = *sl.h_ctrl;
-    const bool done = reinterpret_cast<const volatile int&>(c.done) != 0;
-    const int maxit = plan_max_iter(r->plan);
-    if (r->cancel || done || sl.it_enq >= maxit) {
-      const int status = r->cancel ? PINT_ECANCELED : solve_status(r->plan, c, &r->rep);
-      r->status = status;
-      if (status == PINT_OK) s->predict[sl.cur_key] = c.iter;
-      if (!r->cancel) {
-        if (hipMemcpyAsync(sl.h_out, sl.d_U, r->ns * r->nt * sizeof(double), hipMemcpyDeviceToHost, sl.st) !=
-            hipSuccess)
-          return srv_fail(s, PINT_EHIP, "result copy failed");
-      }
-      if (hipEventRecord(sl.ev, sl.st) != hipSuccess) return srv_fail(s, PINT_EHIP, "hipEventRecord failed");
-      sl.state = SL_DRAINING;
-      return PINT_OK;
-    }
+  const Ctrl& c = *sl.h_ctrl;
+  const bool done = reinterpret_cast<const volatile int&>(c.done) != 0;
+  const int maxit = plan_max_iter(r->plan);
+  if (!(r->cancel || done || sl.it_enq >= maxit)) {
     int rc = enqueue_it(s, sl, sl.it_enq);
     if (rc) return rc;
     ++sl.it_enq;
     if (hipEventRecord(sl.ev, sl.st) != hipSuccess) return srv_fail(s, PINT_EHIP, "hipEventRecord failed");
     return PINT_OK;
   }
-  // draining: the result is in the pinned staging buffer
-  if (!r->cancel) r->result.assign(sl.h_out, sl.h_out + r->ns * r->nt);
+  // every enqueued iteration has finished (the slot's event completed)
+  const int status = r->cancel ? PINT_ECANCELED : solve_status(r->plan, c, &r->rep);
+  if (status == PINT_OK) s->predict[sl.cur_key] = c.iter;
   r->rep.struct_size = sizeof(pint_report);
   r->rep.ms_total = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
-  s->alloc.release(r->pool_off, r->footprint);
+  if (!r->cancel && !r->d_U) {
+    r->held = true;
+    r->d_res = sl.d_U;
+  } else {
+    s->alloc.release(r->pool_off, r->footprint);
+  }
   sl.req = nullptr;
   sl.state = SL_IDLE;
-  finish_req(s, r, r->cancel ? PINT_ECANCELED : r->status);
+  finish_req(s, r, status);
   return PINT_OK;
 }
 
@@ -347,7 +362,10 @@ void worker_main(pint_server* s) {
       s->queue.pop_front();
       r->pool_off = off;
       s->pool_peak = std::max(s->pool_peak, s->alloc.used());
+      const Clock::time_point h0 = Clock::now();
+      g_srv_err.clear();
       const int rc = start_req(s, *free_slot, r);
+      s->host_seconds += std::chrono::duration<double>(Clock::now() - h0).count();
       if (rc) {
         (void)hipStreamSynchronize(free_slot->st);  // pending copies read the plan's host tables
         s->alloc.release(off, r->footprint);
@@ -365,7 +383,10 @@ void worker_main(pint_server* s) {
       any_active = true;
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
+      const Clock::time_point h0 = Clock::now();
+      g_srv_err.clear();
       int rc = q == hipSuccess ? advance(s, sl) : srv_fail(s, PINT_EHIP, "stream error");
+      s->host_seconds += std::chrono::duration<double>(Clock::now() - h0).count();
       if (rc) {
         Req* r = sl.req;
         (void)hipStreamSynchronize(sl.st);
@@ -381,15 +402,78 @@ void worker_main(pint_server* s) {
     }
     if (s->stop && !any_active && s->queue.empty()) break;
     if (!progressed) {
-      if (any_active) {
+      if (any_active) {  // poll the slots' events again after letting submitters in
         lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        std::this_thread::yield();
         lk.lock();
       } else {
         s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
       }
     }
   }
+}
+
+// Shared part of the two submit calls: validate, build the plan, size the
+// footprint, queue.  Exactly one of h_u0 and (d_u0, d_U) is given.
+int submit_common(pint_server* s, const pint_problem* p, const double* h_u0, const double* d_u0, double* d_U,
+                  uint64_t* ticket) {
+  const Clock::time_point t_submit = Clock::now();  // latency includes plan construction
+  pint_problem q = *p;
+  q.flags |= PINT_FLAG_INIT_BROADCAST_U0;
+  q.flags &= ~PINT_FLAG_STAGE_TIMING;
+  PlanOpts o;
+  o.host_mirror = false;
+  o.defer_tables = true;
+  pint_plan* plan = nullptr;
+  int rc = plan_create_ex(&q, o, &plan);
+  if (rc) return srv_fail(s, rc, std::string("invalid problem: ") + pint_last_error());
+  Req* r = new (std::nothrow) Req();
+  if (!r) {
+    pint_plan_destroy(plan);
+    return srv_fail(s, PINT_ENOMEM, "host allocation failed");
+  }
+  r->prob = q;
+  r->plan = plan;
+  r->ns = size_t(plan_ns(plan));
+  r->nt = size_t(plan_nt(plan));
+  r->tab_bytes = plan_table_bytes(&q);
+  r->work_bytes = plan_workspace_bytes(plan);
+  r->d_u0 = d_u0;
+  r->d_U = d_U;
+  if (d_U) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(d_U), b = reinterpret_cast<uintptr_t>(d_u0);
+    const uintptr_t ua = a + r->ns * r->nt * sizeof(double), ub = b + r->ns * sizeof(double);
+    if (a < ub && b < ua) {
+      pint_plan_destroy(plan);
+      delete r;
+      return srv_fail(s, PINT_EINVAL, "d_u0 and d_U overlap");
+    }
+    r->footprint = al256(r->tab_bytes) + al256(r->work_bytes);
+  } else {
+    r->footprint = al256(r->tab_bytes) + al256(r->ns * 8) + al256(r->ns * r->nt * 8) + al256(r->work_bytes);
+  }
+  if (r->footprint > s->alloc.size()) {
+    pint_plan_destroy(plan);
+    delete r;
+    return srv_fail(s, PINT_ENOMEM, "request footprint exceeds the whole pool");
+  }
+  if (h_u0) r->u0.assign(h_u0, h_u0 + r->ns);
+  r->t_submit = t_submit;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->fatal) {
+      pint_plan_destroy(plan);
+      delete r;
+      return srv_fail(s, s->fatal, "server stopped after a HIP error");
+    }
+    r->ticket = s->next_ticket++;
+    s->reqs[r->ticket] = r;
+    s->queue.push_back(r);
+    ++s->n_submitted;
+  }
+  s->cv_work.notify_one();
+  *ticket = r->ticket;
+  return PINT_OK;
 }
 
 }  // namespace
@@ -427,49 +511,15 @@ int pint_server_create(const pint_server_config* cfg, pint_server** out) {
 
 int pint_server_submit(pint_server* s, const pint_problem* p, const double* h_u0, uint64_t* ticket) {
   if (!s || !p || !h_u0 || !ticket) return srv_fail(s, PINT_EINVAL, "NULL argument");
-  pint_problem q = *p;
-  q.flags |= PINT_FLAG_INIT_BROADCAST_U0;
-  q.flags &= ~PINT_FLAG_STAGE_TIMING;
-  PlanOpts o;
-  o.host_mirror = false;
-  o.defer_tables = true;
-  pint_plan* plan = nullptr;
-  int rc = plan_create_ex(&q, o, &plan);
-  if (rc) return srv_fail(s, rc, std::string("invalid problem: ") + pint_last_error());
-  Req* r = new (std::nothrow) Req();
-  if (!r) {
-    pint_plan_destroy(plan);
-    return srv_fail(s, PINT_ENOMEM, "host allocation failed");
-  }
-  r->prob = q;
-  r->plan = plan;
-  r->ns = size_t(plan_ns(plan));
-  r->nt = size_t(plan_nt(plan));
-  r->tab_bytes = plan_table_bytes(&q);
-  r->work_bytes = plan_workspace_bytes(plan);
-  r->footprint = al256(r->tab_bytes) + al256(r->ns * 8) + al256(r->ns * r->nt * 8) + al256(r->work_bytes);
-  if (r->footprint > s->alloc.size()) {
-    pint_plan_destroy(plan);
-    delete r;
-    return srv_fail(s, PINT_ENOMEM, "request footprint exceeds the whole pool");
-  }
-  r->u0.assign(h_u0, h_u0 + r->ns);
-  r->t_submit = Clock::now();
-  {
-    std::lock_guard<std::mutex> g(s->mu);
-    if (s->fatal) {
-      pint_plan_destroy(plan);
-      delete r;
-      return srv_fail(s, s->fatal, "server stopped after a HIP error");
-    }
-    r->ticket = s->next_ticket++;
-    s->reqs[r->ticket] = r;
-    s->queue.push_back(r);
-    ++s->n_submitted;
-  }
-  s->cv_work.notify_one();
-  *ticket = r->ticket;
-  return PINT_OK;
+  return submit_common(s, p, h_u0, nullptr, nullptr, ticket);
+}
+
+int pint_server_submit_device(pint_server* s, const pint_problem* p, const double* d_u0, double* d_U,
+                              uint64_t* ticket) {
+  if (!s || !p || !d_u0 || !d_U || !ticket) return srv_fail(s, PINT_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_u0) % 8 || reinterpret_cast<uintptr_t>(d_U) % 8)
+    return srv_fail(s, PINT_EINVAL, "device buffers must be 8-byte aligned");
+  return submit_common(s, p, nullptr, d_u0, d_U, ticket);
 }
 
 int pint_server_wait(pint_server* s, uint64_t ticket, double* h_U, pint_report* rep, int timeout_ms) {
@@ -479,21 +529,39 @@ int pint_server_wait(pint_server* s, uint64_t ticket, double* h_U, pint_report* 
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return srv_fail(s, PINT_ENOTFOUND, "unknown ticket");
   Req* r = it->second;
+  if (r->waited) return srv_fail(s, PINT_EINVAL, "another thread is already waiting for this ticket");
+  r->waited = true;
   auto ready = [&] { return r->state == RQ_DONE; };
   if (timeout_ms < 0) {
     s->cv_done.wait(lk, ready);
   } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    r->waited = false;
     return srv_fail(s, PINT_ETIMEDOUT, "timed out");
   }
-  const int status = r->status;
-  if (h_U && !r->result.empty()) std::memcpy(h_U, r->result.data(), r->result.size() * sizeof(double));
+  int status = r->status;
+  s->reqs.erase(it);  // the request is ours now: copy out without holding the lock
+  lk.unlock();
+  if (r->held) {
+    if (h_U) {
+      int prev = 0;
+      (void)hipGetDevice(&prev);
+      (void)hipSetDevice(s->device);
+      const hipError_t e = hipMemcpy(h_U, r->d_res, r->ns * r->nt * sizeof(double), hipMemcpyDeviceToHost);
+      (void)hipSetDevice(prev);
+      if (e != hipSuccess) status = srv_fail(s, PINT_EHIP, std::string("result copy: ") + hipGetErrorString(e));
+    }
+    lk.lock();
+    s->alloc.release(r->pool_off, r->footprint);
+    lk.unlock();
+    s->cv_work.notify_one();  // freed pool memory may admit a queued request
+  }
+  if (!r->err.empty() && status == r->status) g_srv_err = r->err;
   if (rep) {
     const size_t sz = rep->struct_size;
     *rep = r->rep;
     rep->struct_size = sz;
     rep->status = status;
   }
-  s->reqs.erase(it);
   delete r;
   return status;
 }
@@ -545,6 +613,7 @@ int pint_server_stats(pint_server* s, pint_server_statistics* st) {
   st->graphs_captured = s->graph_captures;
   st->graph_updates = s->graph_updates;
   st->graph_launches = s->graph_launches;
+  st->worker_host_seconds = s->host_seconds;
   return PINT_OK;
 }
 
@@ -566,7 +635,6 @@ int pint_server_destroy(pint_server* s) {
     if (sl.st) (void)hipStreamDestroy(sl.st);
     if (sl.h_ctrl) (void)hipHostFree(sl.h_ctrl);
     if (sl.h_in) (void)hipHostFree(sl.h_in);
-    if (sl.h_out) (void)hipHostFree(sl.h_out);
   }
   for (auto& kv : s->reqs) {
     if (kv.second->plan) pint_plan_destroy(kv.second->plan);
@@ -576,6 +644,6 @@ int pint_server_destroy(pint_server* s) {
   return PINT_OK;
 }
 
-const char* pint_server_last_error(const pint_server* s) { return s ? s->err.c_str() : g_srv_err.c_str(); }
+const char* pint_server_last_error(const pint_server*) { return g_srv_err.c_str(); }
 
 }  // extern "C"

@@ -35,6 +35,7 @@ class Server:
             self._check(self.lib.dll.pint_server_create(ct.byref(cfg), ct.byref(h)), None)
         self.h = h
         self._shapes = {}
+        self._held = {}
 
     def _check(self, rc, h, ok=(_pint.PINT_OK,)):
         if rc in ok:
@@ -42,27 +43,61 @@ class Server:
         msg = self.lib.dll.pint_server_last_error(h) or b""
         raise _pint.PintError(rc, msg.decode() or self.lib.dll.pint_status_string(rc).decode())
 
+    @staticmethod
+    def _struct(problem, precision, rtol, max_iter):
+        if isinstance(problem, _pint.Problem):
+            return problem
+        p = problem
+        return _pint.make_problem(p.op, p.dim, p.n, p.nt, p.dt, theta=p.theta, eps=p.eps, beta=p.beta,
+                                  alpha=p.alpha, precision=precision, rtol=rtol, max_iter=max_iter)
+
+    @staticmethod
+    def _shape(problem):
+        return (problem.nt,) + ((problem.nx,) if problem.dim == 1 else (problem.ny, problem.nx))
+
     def submit(self, problem, u0: np.ndarray, precision: str = "mixed", rtol: float = 1e-10,
                max_iter: int = 30) -> int:
         """Queue one solve and return its ticket.  ``problem`` is a
         ``pint_problem`` struct, or any object with the fields op, dim, n, nt,
         dt, theta, eps, beta, alpha (then ``precision``, ``rtol`` and
-        ``max_iter`` complete it).  u0 is a host array of one time slice."""
-        if not isinstance(problem, _pint.Problem):
-            p = problem
-            problem = _pint.make_problem(p.op, p.dim, p.n, p.nt, p.dt, theta=p.theta, eps=p.eps, beta=p.beta,
-                                         alpha=p.alpha, precision=precision, rtol=rtol, max_iter=max_iter)
+        ``max_iter`` complete it).  u0 is a host array of one time slice; the
+        result comes back as a host array from ``wait``."""
+        problem = self._struct(problem, precision, rtol, max_iter)
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         ns = problem.nx * (problem.ny if problem.dim == 2 else 1)
         if u0.size != ns:
             raise ValueError(f"u0 has {u0.size} values, the problem's time slice {ns}")
         t = ct.c_uint64()
         self._check(self.lib.dll.pint_server_submit(self.h, ct.byref(problem), u0.ctypes.data, ct.byref(t)), self.h)
-        self._shapes[t.value] = (problem.nt,) + ((problem.nx,) if problem.dim == 1 else (problem.ny, problem.nx))
+        self._shapes[t.value] = self._shape(problem)
+        return t.value
+
+    def submit_device(self, problem, u0: torch.Tensor, U: torch.Tensor, precision: str = "mixed",
+                      rtol: float = 1e-10, max_iter: int = 30, sync: bool = True) -> int:
+        """Device-resident request: u0 ([n]*dim) and U ([nt, n, ...]) are
+        contiguous float64 tensors on the server's device; the solve iterates
+        in place on U, which holds the result once ``wait`` returns.  Both
+        tensors are kept referenced until then.  u0 must hold its values when
+        the server reads it: with ``sync`` the current stream is synchronized
+        here; pass False when the caller has already synchronized."""
+        problem = self._struct(problem, precision, rtol, max_iter)
+        shape = self._shape(problem)
+        for t, sh, name in ((u0, shape[1:], "u0"), (U, shape, "U")):
+            if t.device != self.device or t.dtype != torch.float64 or tuple(t.shape) != sh \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 tensor of shape {sh} on {self.device}")
+        if sync:
+            torch.cuda.current_stream(self.device).synchronize()
+        t = ct.c_uint64()
+        self._check(self.lib.dll.pint_server_submit_device(self.h, ct.byref(problem), u0.data_ptr(), U.data_ptr(),
+                                                           ct.byref(t)), self.h)
+        self._shapes[t.value] = None
+        self._held[t.value] = (u0, U)
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1, raise_on_error: bool = True):
-        """(U, report dict) of a finished request; U is a host array."""
+        """(U, report dict) of a finished request: U is a host array, or the
+        caller's device tensor for a device-resident request."""
         shape = self._shapes.get(ticket)
         out = np.empty(shape, dtype=np.float64) if shape else None
         rep = _pint.Report()
@@ -71,6 +106,9 @@ class Server:
                                            ct.byref(rep), timeout_ms)
         if rc != _pint.PINT_ETIMEDOUT:
             self._shapes.pop(ticket, None)
+            held = self._held.pop(ticket, None)
+            if held is not None:
+                out = held[1]
         ok = (_pint.PINT_OK,) if raise_on_error else (_pint.PINT_OK, _pint.PINT_ENOCONV, _pint.PINT_EDIVERGED,
                                                       _pint.PINT_ECANCELED)
         self._check(rc, self.h, ok=ok)

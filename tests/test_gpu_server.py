@@ -7,6 +7,7 @@ standalone result bit for bit, whatever else is in flight.  The standalone
 solve itself is held to the oracle elsewhere; here a sample of the served
 results is also compared with the sequential oracle directly.
 """
+import ctypes as ct
 import dataclasses
 
 import numpy as np
@@ -156,3 +157,55 @@ def test_cancel_and_timeout():
     assert st["completed"] == 2 and st["cancelled"] == 1
     assert np.array_equal(U3, _solo(tail, u0t, "fp64")[0])
     assert np.array_equal(U1, _solo(head, u0h, "fp64")[0])
+
+
+def test_device_resident_requests():
+    # device-resident and host requests mixed in one server: each device result
+    # equals the standalone solve bit for bit, and only tables + workspace come
+    # from the pool
+    import torch
+    reqs = _stream(8, seed=9)
+    with Server(1 << 30, max_active=4, device=dev()) as srv:
+        bufs, ts = [], []
+        for i, r in enumerate(reqs):
+            u0 = request_u0(r)
+            if i % 2 == 0:
+                d0 = to_dev(u0)
+                dU = torch.full(r.problem.shape, float("nan"), dtype=torch.float64, device=dev())
+                ts.append(srv.submit_device(r.problem, d0, dU, precision=PRECS[i % 3]))
+                bufs.append(dU)
+            else:
+                ts.append(srv.submit(r.problem, u0, precision=PRECS[i % 3]))
+                bufs.append(None)
+        res = [srv.wait(t) for t in ts]
+        st = srv.stats()
+        with pytest.raises(PintError) as e:   # overlapping input and output
+            big = torch.zeros((16 + 1) * 16 * 16, dtype=torch.float64, device=dev())
+            p = Problem(op="biharmonic", dim=2, n=16, nt=16, dt=1e-5)
+            srv._check(srv.lib.dll.pint_server_submit_device(
+                srv.h, ct.byref(srv._struct(p, "fp64", 1e-10, 30)), big.data_ptr() + 8 * 16 * 16,
+                big.data_ptr(), ct.byref(ct.c_uint64())), srv.h)
+        assert e.value.code == _pint.PINT_EINVAL
+    assert st["completed"] == len(reqs)
+    for i, (r, (U, rep)) in enumerate(zip(reqs, res)):
+        ref, _ = _solo(r.problem, request_u0(r), PRECS[i % 3])
+        got = host(U) if bufs[i] is not None else U
+        if bufs[i] is not None:
+            assert U is bufs[i]
+        assert rep["status"] == 0 and np.array_equal(got, ref), f"request {i}"
+
+
+def test_host_results_hold_pool_until_collected():
+    import time
+    p = Problem(op="biharmonic", dim=2, n=32, nt=32, dt=1e-5, alpha=1e-3)
+    u0 = np.random.default_rng(12).uniform(-0.05, 0.05, p.slice_shape)
+    with Server(1 << 26, max_active=2, device=dev()) as srv:
+        t = srv.submit(p, u0, precision="fp64")
+        t_end = time.time() + 60
+        while srv.stats()["completed"] < 1 and time.time() < t_end:
+            time.sleep(1e-3)
+        st = srv.stats()
+        assert st["completed"] == 1 and st["active"] == 0 and st["pool_in_use"] > 0
+        U, rep = srv.wait(t)
+        assert srv.stats()["pool_in_use"] == 0
+    assert np.array_equal(U, _solo(p, u0, "fp64")[0])
