@@ -11,6 +11,7 @@ with the result checked against the CPU FP64 oracle.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import resource
@@ -23,11 +24,16 @@ if ROOT not in sys.path:
 
 METRIC = "space-time DOF/s at 1e-10 rel err vs FP64 oracle; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # dense, MI355X
+BF16_ALPHA = 1e-2  # alpha of the BF16 runs (coarser contraction, larger alpha)
 PREC_DESC = {
     "mixed": "FP64 residual, FP64 forward DCT, FP32 time FFT solve and inverse DCT, FP64 update "
              "(iterative refinement)",
     "fp32": "FP64 residual, FP32 DCTs and time FFT solve, FP64 update (iterative refinement)",
     "fp64": "FP64 throughout",
+    "bf16": "FP64 residual and forward DCT, BF16-operand MFMA time contraction (FP32 accumulate), FP32 inverse "
+            "DCT, FP64 update",
+    "bf16x3": "as bf16 with a two-term BF16 split of both operands (three products)",
 }
 
 WORKLOADS = {
@@ -266,8 +272,9 @@ def main():
         log(f"calibration copy: {nb * 4} bytes read, {nb * 4} bytes written")
         del a, b
 
-    def run(prec, steps, warmup, timing):
-        s = Solver.for_problem(p, precision=prec, device=dev, stage_timing=timing)
+    def run(prec, steps, warmup, timing, time_path="auto", alpha=None):
+        q = p if alpha is None else dataclasses.replace(p, alpha=alpha)
+        s = Solver.for_problem(q, precision=prec, device=dev, stage_timing=timing, time_path=time_path)
         U = torch.empty(p.shape, dtype=torch.float64, device=dev)
         for _ in range(warmup):
             s.solve(u0, U)
@@ -348,16 +355,33 @@ def main():
         "algo_bytes_per_dof_iteration": sum(steady.values()),
     }
     if not args.no_fp64_compare:
-        # the other precision modes, same workload and step count (not timed with events)
+        # the other precision modes and the dense time contraction, same
+        # workload and step count (value loop without events; the dense
+        # variants get a second loop with events for the contraction kernel)
         out["paths"] = {}
-        for other in ("mixed", "fp32", "fp64"):
-            if other == args.precision:
-                continue
-            elo, _, repso, Uo = run(other, args.steps, args.warmup, False)
-            log(f"{other} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
-            out["paths"][other] = {"value": p.dof * args.steps / elo, "ms_per_step": elo / args.steps * 1e3,
-                                   "iterations": repso[-1]["iterations"],
-                                   "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref)}
+        variants = [(o, "fft", None) for o in ("mixed", "fp32", "fp64") if o != args.precision]
+        variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", BF16_ALPHA),
+                     ("bf16", "dense", BF16_ALPHA)]
+        for prec, tp, al in variants:
+            key = prec if tp == "fft" else f"{prec}_dense"
+            elo, _, repso, Uo = run(prec, args.steps, args.warmup, False, tp, al)
+            log(f"{key} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
+            d = {"value": p.dof * args.steps / elo, "ms_per_step": elo / args.steps * 1e3,
+                 "iterations": repso[-1]["iterations"], "alpha": repso[-1]["alpha"],
+                 "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref)}
+            if tp == "dense":
+                _, _, repe, _ = run(prec, args.steps, args.warmup, True, tp, al)
+                its = sum(r["iterations"] for r in repe)
+                us = sum(r["ms_stage"][2] for r in repe) / max(1, its) * 1e3
+                flops = 4.0 * p.nt * p.dof * (3 if prec == "bf16x3" else 1)
+                peak = MFMA_PEAK_TFLOPS["bf16" if prec.startswith("bf16") else "fp32"]
+                ach = flops / (us * 1e-6) / 1e12
+                d["time_contraction"] = {"bound": "mfma", "kernel": "k_time_dense", "avg_launch_us": us,
+                                         "flops_per_launch": flops, "achieved": ach, "peak": peak,
+                                         "unit": "TFLOP/s", "frac": ach / peak,
+                                         "hbm_gbs": 8.0 * p.dof / (us * 1e-6) / 1e9}
+                log(f"{key}: contraction {us:.1f} us, {ach:.1f} TFLOP/s ({100 * ach / peak:.1f}% of {peak})")
+            out["paths"][key] = d
     if not args.no_serving:
         out["serving"] = serving_bench(dev, args.precision, args.serve_slots, args.serve_pool_gib,
                                        args.serve_requests, oracle_checks=8, graphs=not args.serve_no_graphs)

@@ -71,7 +71,9 @@ extern "C" {
 #define PINT_PREC_FP32_REFINE   1  /* transforms/divide FP32, residual+update FP64 */
 #define PINT_PREC_FP32_NOREFINE 2  /* residual and update in FP32 too          */
 #define PINT_PREC_BF16_REFINE   3  /* dense time contraction with BF16 operands,
-                                      FP32 accumulate; residual+update FP64    */
+                                      FP32 accumulate (time path AUTO or DENSE);
+                                      forward spatial DCT FP64 as for MIXED,
+                                      inverse FP32; residual+update FP64      */
 #define PINT_PREC_MIXED         4  /* forward spatial DCT in FP64 (its rounding
                                       would be amplified by the stiffness ratio
                                       of the shifted spatial solves), time solve
@@ -79,14 +81,22 @@ extern "C" {
                                       FP64                                     */
 
 /* ------------------------------------------------------------- time path */
-#define PINT_TIME_AUTO  0          /* FFT over time (alpha-circulant)          */
+#define PINT_TIME_AUTO  0          /* FFT over time (alpha-circulant); the
+                                      dense path for PINT_PREC_BF16_REFINE    */
 #define PINT_TIME_FFT   1          /* batched FFT over the time index          */
 #define PINT_TIME_DENSE 2          /* dense contraction over the time index on
-                                      the matrix cores (FP32 or BF16 MFMA)     */
+                                      the matrix cores: FP32 MFMA for
+                                      FP32_REFINE / MIXED, BF16 MFMA for
+                                      BF16_REFINE; FP32 accumulation.  Needs
+                                      N_t >= 32 and N_s a multiple of
+                                      max(32, 4096 / N_t); not for FP64       */
 
 /* ----------------------------------------------------------------- flags */
 #define PINT_FLAG_INIT_BROADCAST_U0 0x1u /* fill d_U with u0 before iterating */
 #define PINT_FLAG_STAGE_TIMING      0x2u /* fill pint_report.ms_stage (adds syncs) */
+#define PINT_FLAG_BF16_SPLIT        0x4u /* PINT_PREC_BF16_REFINE: two-term BF16
+                                            split of both operands, three
+                                            products (hi*hi + hi*lo + lo*hi) */
 
 #define PINT_HIST 64
 

@@ -19,10 +19,11 @@ PINT_ECANCELED = -7
 PINT_ENOTFOUND = -8
 
 OPS = {"biharmonic": 0, "linear_ch": 1, "ch": 2, "ch_eyre": 3}
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3, "mixed": 4}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3, "mixed": 4, "bf16x3": 3}
 TIME_PATHS = {"auto": 0, "fft": 1, "dense": 2}
 FLAG_INIT_BROADCAST_U0 = 0x1
 FLAG_STAGE_TIMING = 0x2
+FLAG_BF16_SPLIT = 0x4
 HIST = 64
 
 # Every symbol include/pint.h declares (checked by the CPU test suite).
@@ -162,6 +163,8 @@ def make_problem(op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1
     p.beta = beta
     p.alpha = alpha
     p.precision = PRECISIONS[precision]
+    if precision == "bf16x3":  # BF16 with the two-term operand split
+        flags |= FLAG_BF16_SPLIT
     p.time_path = TIME_PATHS[time_path]
     p.rtol = rtol
     p.max_iter = max_iter

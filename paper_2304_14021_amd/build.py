@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpint.so")
-SOURCES = ["kernels.hip", "pint_api.hip", "pint_server.hip"]
+SOURCES = ["kernels.hip", "time_dense.hip", "pint_api.hip", "pint_server.hip"]
 ARCH = os.environ.get("PINT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

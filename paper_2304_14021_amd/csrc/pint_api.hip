@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -46,6 +47,7 @@ struct pint_plan {
   double safety = 0.1;
   bool fp64;   // working precision W = double
   bool mixed;  // FP64 forward spatial transform, FP32 time solve and inverse
+  int dense = -1;  // DenseKind of the time contraction on the matrix cores, -1: FFT path
   std::string err;
 
   // device tables (one allocation), FP64 then FP32 copies
@@ -54,6 +56,8 @@ struct pint_plan {
   size_t tab_bytes = 0;
   std::vector<unsigned char> host_tab;  // kept alive for asynchronous table copies
   size_t offs_d[11] = {}, offs_f[11] = {};  // table offsets (FP64 / FP32 copies) in the block
+  size_t offs_w[4] = {};                     // dense W tables: F32 (wf, wb) or BF16 (wf hi/lo, wb hi/lo)
+  DenseArgs dargs{};
   DctTables<double> dtd{};
   DctTables<float> dtf{};
   TimeArgs<double> tad{};
@@ -114,6 +118,13 @@ double mu_min(const pint_problem& p, int dim, int n, double h) {
   return best;
 }
 
+// Kind of dense time contraction a problem asks for (-1: the FFT path).
+int dense_kind_of(const pint_problem* p) {
+  if (p->precision == PINT_PREC_BF16_REFINE) return (p->flags & PINT_FLAG_BF16_SPLIT) ? DK_BF16X3 : DK_BF16;
+  if (p->time_path == PINT_TIME_DENSE) return DK_F32;
+  return -1;
+}
+
 int validate(const pint_problem* p, std::string* err) {
   if (!p) return set_err(err, PINT_EINVAL, "problem is NULL");
   if (p->struct_size < sizeof(pint_problem)) return set_err(err, PINT_EINVAL, "pint_problem.struct_size too small");
@@ -132,10 +143,22 @@ int validate(const pint_problem* p, std::string* err) {
     return set_err(err, PINT_EINVAL, "the CH schemes are backward Euler (theta = 1)");
   if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
   if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
-  if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED)
+  if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED &&
+      p->precision != PINT_PREC_BF16_REFINE)
     return set_err(err, PINT_EINVAL, "precision not supported by this build");
-  if (p->time_path != PINT_TIME_AUTO && p->time_path != PINT_TIME_FFT)
-    return set_err(err, PINT_EINVAL, "time path not supported by this build");
+  if (p->time_path != PINT_TIME_AUTO && p->time_path != PINT_TIME_FFT && p->time_path != PINT_TIME_DENSE)
+    return set_err(err, PINT_EINVAL, "unknown time path");
+  if (p->precision == PINT_PREC_FP64 && p->time_path == PINT_TIME_DENSE)
+    return set_err(err, PINT_EINVAL, "the dense time contraction computes in FP32 or BF16, not FP64");
+  if (p->precision == PINT_PREC_BF16_REFINE && p->time_path == PINT_TIME_FFT)
+    return set_err(err, PINT_EINVAL, "BF16 is a precision of the dense time contraction, not of the FFT path");
+  if (dense_kind_of(p) >= 0) {
+    const int nb = dense_cols_per_block(p->nt);
+    const int ns = p->dim == 2 ? p->nx * p->nx : p->nx;
+    if (nb == 0 || ns % nb != 0)
+      return set_err(err, PINT_EINVAL, "the dense time contraction needs N_t >= 32 and N_s a multiple of " +
+                                           std::to_string(nb ? nb : 32));
+  }
   if (p->max_iter < 0 || p->max_iter > PINT_HIST) return set_err(err, PINT_EINVAL, "max_iter must be in [0, 64]");
   if (p->rtol < 0.0) return set_err(err, PINT_EINVAL, "rtol must be >= 0");
   const double lx = p->lx > 0 ? p->lx : 1.0;
@@ -244,6 +267,87 @@ Offs put_all(std::vector<unsigned char>& buf, const HostTables& t) {
   return o;
 }
 
+// Space for the dense time-contraction matrices (each N_t x N_t, 256-byte
+// aligned): DK_F32 two FP32 arrays, the BF16 kinds four BF16 arrays.
+void reserve_dense(std::vector<unsigned char>& buf, int kind, int nt, size_t* offs) {
+  if (kind < 0) return;
+  const size_t bytes = size_t(nt) * nt * (kind == DK_F32 ? 4 : 2);
+  const int count = kind == DK_F32 ? 2 : 4;
+  for (int i = 0; i < count; ++i) {
+    offs[i] = align256(buf.size());
+    buf.resize(offs[i] + bytes);
+  }
+}
+
+uint16_t bf16_round(float f) {  // round to nearest even (finite values)
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// The dense forward and inverse time matrices of one spatial mode (FP64):
+//   W_f[r][n] = a^n {1, (-1)^n, cos(2 pi l n/N_t), -sin(2 pi l n/N_t)}        r = 0, 1, 2l, 2l+1
+//   W_b[n][r] = a^{-n}/N_t {1, (-1)^n, 2 cos(2 pi l n/N_t), -2 sin(2 pi l n/N_t)}
+// so that W_b diag-divide W_f is Gamma^{-1} F^{-1} D^{-1} F Gamma on real data
+// (Section 2.1, eq. pintiter1), with the Hermitian half-spectrum packed into
+// N_t real rows.  Stored as FP32 transposes (DK_F32) or BF16 hi/lo row-major.
+void put_dense(std::vector<unsigned char>& buf, const pint_plan* pl, const size_t* offs) {
+  const int nt = pl->nt;
+  const double la = std::log(pl->alpha) / nt;
+  std::vector<double> wf(size_t(nt) * nt), wb(size_t(nt) * nt);
+  for (int r = 0; r < nt; ++r) {
+    const int l = r >> 1;
+    for (int n = 0; n < nt; ++n) {
+      const double an = std::exp(la * n), ain = std::exp(-la * n) / nt;
+      const double ang = 2.0 * M_PI * double((long(l) * n) % nt) / nt;
+      const double sgn = (n & 1) ? -1.0 : 1.0;
+      double f, b;
+      if (r == 0) {
+        f = an;
+        b = ain;
+      } else if (r == 1) {
+        f = an * sgn;
+        b = ain * sgn;
+      } else if ((r & 1) == 0) {
+        f = an * std::cos(ang);
+        b = 2.0 * ain * std::cos(ang);
+      } else {
+        f = -an * std::sin(ang);
+        b = -2.0 * ain * std::sin(ang);
+      }
+      wf[size_t(r) * nt + n] = f;  // W_f[r][n]
+      wb[size_t(n) * nt + r] = b;  // W_b[n][r]
+    }
+  }
+  if (pl->dense == DK_F32) {
+    float* tf = reinterpret_cast<float*>(buf.data() + offs[0]);
+    float* tb = reinterpret_cast<float*>(buf.data() + offs[1]);
+    for (int m = 0; m < nt; ++m)
+      for (int k = 0; k < nt; ++k) {
+        tf[size_t(k) * nt + m] = float(wf[size_t(m) * nt + k]);
+        tb[size_t(k) * nt + m] = float(wb[size_t(m) * nt + k]);
+      }
+    return;
+  }
+  const std::vector<double>* src[2] = {&wf, &wb};
+  for (int w = 0; w < 2; ++w) {
+    uint16_t* hi = reinterpret_cast<uint16_t*>(buf.data() + offs[2 * w]);
+    uint16_t* lo = reinterpret_cast<uint16_t*>(buf.data() + offs[2 * w + 1]);
+    for (size_t i = 0; i < size_t(nt) * nt; ++i) {
+      const double v = (*src[w])[i];
+      hi[i] = bf16_round(float(v));
+      lo[i] = bf16_round(float(v - double(bf16_value(hi[i]))));
+    }
+  }
+}
+
 void store_offs(const Offs& o, size_t* dst) {
   const size_t v[11] = {o.tw_s, o.wq, o.wi, o.tw_t, o.lam1, o.pco, o.qco, o.aj, o.aij, o.lamx, o.lamy};
   for (int i = 0; i < 11; ++i) dst[i] = v[i];
@@ -339,6 +443,16 @@ TimeArgs<float> time_args<float>(const pint_plan* pl) { return pl->taf; }
 // control.  TF is the type of the forward spatial transform, T that of the
 // time solve and the inverse transform.  bcast: the iterate is the broadcast
 // datum u0 (first iteration).
+// a3-a5 on the plan's time path: the FFT kernel, or the dense contraction on
+// the matrix cores (FP32 working type only).
+template <typename T>
+hipError_t launch_time_any(const pint_plan* pl, T* S, const TimeArgs<T>& ta, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (pl->dense >= 0) return launch_time_dense(pl->dense, pl->nt, S, ta, pl->dargs, st);
+  }
+  return launch_time<T>(pl->nt, S, ta, st);
+}
+
 template <typename TF, typename T>
 int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st,
                       hipEvent_t* evs, bool bcast, Ctrl* host) {
@@ -368,7 +482,7 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   if (pl->dim == 2)
     HIPCHK((launch_cols<TF, T>(pl->n, SF, S, done, dct_tables<TF>(pl), pl->nt, false, st)), "y-DCT kernel");
   HIPCHK(ev(2), "hipEventRecord");
-  HIPCHK(launch_time<T>(pl->nt, S, ta, st), "time-solve kernel");
+  HIPCHK(launch_time_any<T>(pl, S, ta, st), "time-solve kernel");
   HIPCHK(ev(3), "hipEventRecord");
   if (pl->dim == 2)
     HIPCHK((launch_cols<T, T>(pl->n, S, S, done, dct_tables<T>(pl), pl->nt, true, st)), "y-DCT-III kernel");
@@ -457,7 +571,9 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   pl->rtol = p->rtol > 0 ? p->rtol : 1e-10;
   pl->max_iter = p->max_iter > 0 ? p->max_iter : 30;
   pl->fp64 = p->precision == PINT_PREC_FP64;
-  pl->mixed = p->precision == PINT_PREC_MIXED;
+  // BF16 keeps the FP64 forward spatial transform of the mixed mode
+  pl->mixed = p->precision == PINT_PREC_MIXED || p->precision == PINT_PREC_BF16_REFINE;
+  pl->dense = dense_kind_of(p);
   pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
   if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {
     delete pl;
@@ -511,6 +627,8 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   std::vector<unsigned char>& buf = pl->host_tab;
   store_offs(put_all<double>(buf, t), pl->offs_d);
   store_offs(put_all<float>(buf, t), pl->offs_f);
+  reserve_dense(buf, pl->dense, pl->nt, pl->offs_w);
+  if (pl->dense >= 0) put_dense(buf, pl, pl->offs_w);
   pl->tab_bytes = align256(buf.size());
   if (!opts.defer_tables) {
     void* mem = opts.d_tables;
@@ -560,11 +678,21 @@ int plan_bind_tables(pint_plan* pl, void* d_mem, hipStream_t st, bool copy) {
   unsigned char* base = static_cast<unsigned char*>(d_mem);
   bind<double>(load_offs(pl->offs_d), base, pl, pl->dtd, pl->tad);
   bind<float>(load_offs(pl->offs_f), base, pl, pl->dtf, pl->taf);
+  pl->dargs = DenseArgs{};
+  if (pl->dense == DK_F32) {
+    pl->dargs.wf = reinterpret_cast<const float*>(base + pl->offs_w[0]);
+    pl->dargs.wb = reinterpret_cast<const float*>(base + pl->offs_w[1]);
+  } else if (pl->dense >= 0) {
+    pl->dargs.wf_hi = base + pl->offs_w[0];
+    pl->dargs.wf_lo = base + pl->offs_w[1];
+    pl->dargs.wb_hi = base + pl->offs_w[2];
+    pl->dargs.wb_lo = base + pl->offs_w[3];
+  }
   return PINT_OK;
 }
 
 size_t plan_table_bytes(const pint_problem* p) {
-  // the table block depends only on N and N_t
+  // the table block depends only on N, N_t and the time path
   HostTables t;
   t.tw_s.resize(p->nx);
   t.wq.resize(p->nx);
@@ -580,6 +708,8 @@ size_t plan_table_bytes(const pint_problem* p) {
   std::vector<unsigned char> buf;
   put_all<double>(buf, t);
   put_all<float>(buf, t);
+  size_t offs[4];
+  reserve_dense(buf, dense_kind_of(p), p->nt, offs);
   return align256(buf.size());
 }
 
@@ -736,11 +866,11 @@ int pint_time_solve(pint_plan* pl, void* d_S, double c_bar, void* stream) {
   if (pl->fp64) {
     TimeArgs<double> ta = pl->tad;
     ta.cbar_val = c_bar;
-    e = launch_time<double>(pl->nt, static_cast<double*>(d_S), ta, st);
+    e = launch_time_any<double>(pl, static_cast<double*>(d_S), ta, st);
   } else {
     TimeArgs<float> ta = pl->taf;
     ta.cbar_val = c_bar;
-    e = launch_time<float>(pl->nt, static_cast<float*>(d_S), ta, st);
+    e = launch_time_any<float>(pl, static_cast<float*>(d_S), ta, st);
   }
   if (e != hipSuccess) return hip_fail(pl, e, "time-solve kernel");
   return PINT_OK;

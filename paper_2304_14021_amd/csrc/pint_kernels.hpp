@@ -123,6 +123,23 @@ hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& d
                       hipStream_t st);
 template <typename T>
 hipError_t launch_time(int nt, T* S, const TimeArgs<T>& ta, hipStream_t st);
+
+// Dense time contraction on the matrix cores (FP32 S, in place).  The W tables
+// are N_t x N_t: for DK_F32 transposed FP32 copies ([k][m]) of W_f and W_b, for
+// the BF16 kinds row-major BF16 hi / lo parts.
+enum DenseKind { DK_F32 = 0, DK_BF16 = 1, DK_BF16X3 = 2 };
+struct DenseArgs {
+  const float* wf;   // W_f^T (DK_F32)
+  const float* wb;   // W_b^T (DK_F32)
+  const void* wf_hi; // BF16 W_f, hi / lo parts (BF16 kinds)
+  const void* wf_lo;
+  const void* wb_hi;
+  const void* wb_lo;
+};
+// Spatial modes per workgroup of the dense path (0 if N_t is too small).
+int dense_cols_per_block(int nt);
+hipError_t launch_time_dense(int kind, int nt, float* S, const TimeArgs<float>& ta, const DenseArgs& da,
+                             hipStream_t st);
 template <typename TI, typename TO>
 hipError_t launch_cast(const TI* in, TO* out, size_t n, hipStream_t st);
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st);

@@ -1,0 +1,119 @@
+"""The dense time contraction on the matrix cores (time path DENSE; GPU).
+
+For each spatial cosine mode the kernel applies W_b diag-divide W_f, with W_f,
+W_b the real N_t x N_t matrices of Gamma_alpha and the Hermitian-packed DFT
+(Section 2.1, eq. pintiter1 Steps 1-3).  The reference is the oracle's
+``time_solve_modal``: one dense alpha-circulant solve per mode by
+numpy.linalg.solve, FP64 (no transform, no packing).
+
+Tolerances, from the arithmetic: a product over the time index of length N_t
+accumulates in FP32 with rounding growing like sqrt(N_t) per output (inputs
+rounded to the operand type, unit roundoff u), and the a^{-n} scaling of the
+inverse turns absolute errors into relative ones multiplied by up to 1/alpha.
+With about four roundings of unit roundoff u per path (input, W_f, divide,
+W_b; the FP32 accumulation adds sqrt(N_t) 2^-24):
+  error <= 4 u sqrt(N_t) / alpha  (relative to max |y|),
+with u = 2^-24 (FP32 operands), 2^-8 (BF16), 2^-16 (BF16 two-term split).
+For single-product BF16 this bound exceeds 1 at small alpha, so its stage
+cases use alpha = 0.25-0.45 (bound < 0.4); a misplaced index or sign gives
+errors of order 1 and fails them.
+End to end, the FP64 residual and update of the outer iteration restore the
+1e-10 bar of the paper's error norm for every kind.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import allatonce as aao
+from oracle import stepper
+from paper_2304_14021_amd import PintError, Solver
+from workloads import Problem
+from tests._gpu import dev, host, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U = {"fp32": 2.0 ** -24, "mixed": 2.0 ** -24, "bf16": 2.0 ** -8, "bf16x3": 2.0 ** -16}
+
+CASES = [
+    Problem(op="linear_ch", dim=1, n=512, nt=64, dt=1e-6, theta=0.5, eps=0.05, beta=0.5, alpha=0.02),
+    Problem(op="linear_ch", dim=2, n=32, nt=64, dt=1e-5, eps=0.05, beta=0.5, alpha=0.01),
+    Problem(op="ch", dim=2, n=64, nt=32, dt=1e-6, eps=0.02, alpha=0.01),
+    Problem(op="biharmonic", dim=1, n=32, nt=1024, dt=1e-6, alpha=0.05),
+    Problem(op="linear_ch", dim=2, n=16, nt=128, dt=1e-5, theta=0.5, eps=0.05, beta=0.5, alpha=0.02),
+    Problem(op="ch_eyre", dim=2, n=32, nt=256, dt=1e-5, eps=0.05, alpha=0.02),
+    Problem(op="biharmonic", dim=2, n=64, nt=512, dt=1e-6, alpha=0.05),
+]
+IDS = [f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}" for p in CASES]
+
+
+BF16_CASES = [
+    Problem(op="biharmonic", dim=2, n=32, nt=32, dt=1e-5, alpha=0.25),
+    Problem(op="linear_ch", dim=1, n=256, nt=64, dt=1e-6, theta=0.5, eps=0.05, beta=0.5, alpha=0.45),
+    Problem(op="ch", dim=2, n=16, nt=128, dt=1e-6, eps=0.05, alpha=0.45),
+]
+STAGE = [(p, prec) for p in CASES for prec in ("fp32", "bf16x3")] + [(p, "bf16") for p in BF16_CASES]
+STAGE_IDS = [f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}-{prec}" for p, prec in STAGE]
+
+
+@pytest.mark.parametrize("p,prec", STAGE, ids=STAGE_IDS)
+def test_dense_time_solve_stage(p, prec):
+    say(f"dense time-solve stage {prec} {p}")
+    rng = np.random.default_rng(15)
+    xh = rng.standard_normal(p.shape).astype(np.float32)
+    c_bar = 0.37 if p.op in ("ch", "ch_eyre") else 0.0
+    s = Solver.for_problem(p, precision=prec, time_path="dense", device=dev())
+    import torch
+    y = host(s.time_solve(to_dev(xh, torch.float32), c_bar))
+    ref = aao.time_solve_modal(p, xh.astype(np.float64), c_bar)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    tol = 4 * U[prec] * math.sqrt(p.nt) / p.alpha
+    assert tol < 0.5
+    say(f"  err {err:.2e} tol {tol:.2e}")
+    assert err < tol, (err, tol)
+
+
+SOLVES = [
+    (Problem(op="linear_ch", dim=2, n=64, nt=128, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3), ["mixed", "fp32"]),
+    (Problem(op="linear_ch", dim=2, n=64, nt=128, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-2), ["bf16", "bf16x3"]),
+    (Problem(op="biharmonic", dim=2, n=32, nt=64, dt=1e-5, theta=0.5, alpha=1e-2), ["mixed", "bf16x3"]),
+    (Problem(op="ch", dim=2, n=64, nt=64, dt=1e-6, eps=0.02, alpha=1e-2), ["mixed", "bf16", "bf16x3"]),
+    (Problem(op="ch_eyre", dim=1, n=128, nt=256, dt=1e-5, eps=0.05, alpha=1e-2), ["fp32", "bf16x3"]),
+]
+SOLVE_IDS = [f"{p.op}-{p.dim}d-n{p.n}-nt{p.nt}" for p, _ in SOLVES]
+
+
+@pytest.mark.parametrize("p,precs", SOLVES, ids=SOLVE_IDS)
+def test_dense_solve_against_oracle(p, precs):
+    rng = np.random.default_rng(21)
+    amp = 0.3 if p.op in ("ch", "ch_eyre") else 0.05
+    u0 = rng.uniform(-amp, amp, p.slice_shape)
+    ref = stepper.sequential(p, u0)
+    for prec in precs:
+        s = Solver.for_problem(p, precision=prec, time_path="dense" if prec in ("mixed", "fp32") else "auto",
+                               device=dev(), max_iter=40)
+        U, rep = s.solve(to_dev(u0), raise_on_error=False)
+        err = stepper.rel_err(host(U), ref)
+        say(f"  {p.op} {prec}: status {rep['status']} iterations {rep['iterations']} err {err:.2e}")
+        assert rep["status"] == 0 and err <= 1e-10
+
+
+def test_dense_equals_fft_path_fixed_point():
+    # both time paths converge to the same sequential solution; their results
+    # agree to the stopping tolerance
+    p = Problem(op="linear_ch", dim=2, n=32, nt=64, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)
+    u0 = np.random.default_rng(4).uniform(-0.05, 0.05, p.slice_shape)
+    a, _ = Solver.for_problem(p, precision="mixed", time_path="dense", device=dev()).solve(to_dev(u0))
+    b, _ = Solver.for_problem(p, precision="mixed", time_path="fft", device=dev()).solve(to_dev(u0))
+    assert stepper.rel_err(host(a), host(b)) <= 2e-10
+
+
+def test_dense_rejections():
+    with pytest.raises(PintError):  # FP64 has no dense kind
+        Solver(op="biharmonic", dim=2, n=32, nt=64, dt=1e-5, precision="fp64", time_path="dense", device=dev())
+    with pytest.raises(PintError):  # BF16 exists only on the dense path
+        Solver(op="biharmonic", dim=2, n=32, nt=64, dt=1e-5, precision="bf16", time_path="fft", device=dev())
+    with pytest.raises(PintError):  # N_t below one MFMA block
+        Solver(op="biharmonic", dim=2, n=32, nt=16, dt=1e-5, precision="fp32", time_path="dense", device=dev())
+    with pytest.raises(PintError):  # N_s not a multiple of the 128 columns per workgroup at N_t = 32
+        Solver(op="biharmonic", dim=1, n=64, nt=32, dt=1e-5, precision="fp32", time_path="dense", device=dev())
