@@ -55,41 +55,86 @@ __device__ __forceinline__ void gemm_tile(f32x16 (&acc)[BPW], const int (&rb)[BP
   constexpr int LD = NB + DPAD;
 #pragma unroll
   for (int q = 0; q < BPW; ++q) acc[q] = f32x16{};
+  // Operands of chunk c + 1 are loaded while the MFMAs of chunk c run; the
+  // chunk shrinks as the blocks per wave grow so the buffers stay small.
   if constexpr (KIND == DK_F32) {
     // A^T is stored [k][m]: a half-wave reads 32 consecutive floats
-#pragma unroll 4
-    for (int k0 = 0; k0 < NTT; k0 += 2) {
-      const int k = k0 + hi;
+    constexpr int KS = BPW >= 8 ? 2 : (BPW >= 4 ? 4 : 8);  // MFMA k-steps (of 2) per chunk
+    constexpr int NCH = NTT / (2 * KS);
+    float ca[KS][BPW], cx_[KS][BPW], na[KS][BPW], nx[KS][BPW];
+    auto load = [&](int c, float (&a)[KS][BPW], float (&b)[KS][BPW]) {
 #pragma unroll
-      for (int q = 0; q < BPW; ++q) {
-        const float a = at[size_t(k) * NTT + rb[q] * 32 + li];
-        const float b = xs[k * LD + cb[q] * 32 + li];
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[q], 0, 0, 0);
+      for (int s = 0; s < KS; ++s) {
+        const int k = c * 2 * KS + 2 * s + hi;
+#pragma unroll
+        for (int q = 0; q < BPW; ++q) {
+          a[s][q] = at[size_t(k) * NTT + rb[q] * 32 + li];
+          b[s][q] = xs[k * LD + cb[q] * 32 + li];
+        }
       }
+    };
+    load(0, ca, cx_);
+    for (int c = 0; c < NCH; ++c) {
+      if (c + 1 < NCH) load(c + 1, na, nx);
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int q = 0; q < BPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[s][q], cx_[s][q], acc[q], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int q = 0; q < BPW; ++q) {
+          ca[s][q] = na[s][q];
+          cx_[s][q] = nx[s][q];
+        }
     }
   } else {
     // A is stored [m][k] in BF16: each lane reads 8 consecutive k (16 bytes)
-#pragma unroll 2
-    for (int k0 = 0; k0 < NTT; k0 += 16) {
-      const int kb = k0 + 8 * hi;
+    constexpr bool X3 = KIND == DK_BF16X3;
+    constexpr int KS = BPW >= 4 ? 1 : 2;  // MFMA k-steps (of 16) per chunk
+    constexpr int NCH = NTT / (16 * KS);
+    bf16x8 ch[KS][BPW], cl[KS][BPW], nh[KS][BPW], nl[KS][BPW];
+    auto load = [&](int c, bf16x8 (&h)[KS][BPW], bf16x8 (&l)[KS][BPW]) {
 #pragma unroll
-      for (int q = 0; q < BPW; ++q) {
-        const size_t ao = size_t(rb[q] * 32 + li) * NTT + kb;
-        const bf16x8 a_hi = *reinterpret_cast<const bf16x8*>(ah + ao);
-        bf16x8 b_hi, b_lo;
+      for (int s = 0; s < KS; ++s) {
+        const int kb = (c * KS + s) * 16 + 8 * hi;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float x = xs[(kb + j) * LD + cb[q] * 32 + li];
-          b_hi[j] = __bf16(x);
-          if constexpr (KIND == DK_BF16X3) b_lo[j] = __bf16(x - float(b_hi[j]));
-        }
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, b_hi, acc[q], 0, 0, 0);
-        if constexpr (KIND == DK_BF16X3) {
-          const bf16x8 a_lo = *reinterpret_cast<const bf16x8*>(al + ao);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, b_lo, acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo, b_hi, acc[q], 0, 0, 0);
+        for (int q = 0; q < BPW; ++q) {
+          const size_t ao = size_t(rb[q] * 32 + li) * NTT + kb;
+          h[s][q] = *reinterpret_cast<const bf16x8*>(ah + ao);
+          if constexpr (X3) l[s][q] = *reinterpret_cast<const bf16x8*>(al + ao);
         }
       }
+    };
+    load(0, ch, cl);
+    for (int c = 0; c < NCH; ++c) {
+      if (c + 1 < NCH) load(c + 1, nh, nl);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int kb = (c * KS + s) * 16 + 8 * hi;
+#pragma unroll
+        for (int q = 0; q < BPW; ++q) {
+          bf16x8 b_hi, b_lo;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float x = xs[(kb + j) * LD + cb[q] * 32 + li];
+            b_hi[j] = __bf16(x);
+            if constexpr (X3) b_lo[j] = __bf16(x - float(b_hi[j]));
+          }
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch[s][q], b_hi, acc[q], 0, 0, 0);
+          if constexpr (X3) {
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch[s][q], b_lo, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl[s][q], b_hi, acc[q], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int q = 0; q < BPW; ++q) {
+          ch[s][q] = nh[s][q];
+          if constexpr (X3) cl[s][q] = nl[s][q];
+        }
     }
   }
 }
