@@ -40,7 +40,16 @@ WORKLOADS = {
     "c2": "2D linearized CH u_t = -beta^2 Lap u - eps^2 Lap^2 u, beta=0.5, eps=0.05, unit square, Neumann, "
           "128x128 cells x 128 backward-Euler levels, dt=1e-5, u0 ~ U[-0.05,0.05] (seed 2)",
     "c1": "1D biharmonic heat, 64 cells x 32 backward-Euler levels, T=1e-3, u0=cos(pi x)+0.5cos(3 pi x)+1e-3 N(0,1)",
+    "c3": "2D nonlinear CH (PinT-I), f(u)=u^3-u, eps=0.01, unit square, Neumann, 256x256 cells x 256 levels, dt=1e-6, "
+          "u0 ~ U[-0.1,0.1] (seed 3)",
+    "c5": "2D nonlinear CH (PinT-I), eps=0.0075, unit square, Neumann, 512x512 cells x 1024 levels, dt=1e-6, "
+          "u0 ~ U[-0.05,0.05] (seed 5)",
 }
+# Configurations whose sequential oracle finishes in seconds are checked
+# against it here; the larger ones are checked by the GPU tests (stored oracle
+# samples for 256^2 x 256, oracle single steps for 512^2 x 1024) and report
+# mass conservation and energy decay here.
+ORACLE_IN_BENCH = ("c1", "c2")
 
 # Algorithmic HBM bytes per space-time DOF per launch of each kernel (working
 # type W = 4 bytes for the FP32-refined path, 8 for FP64).  Steady iterations:
@@ -295,10 +304,20 @@ def main():
     el, lat, reps, U = run(args.precision, args.steps, args.warmup, False)
     value = p.dof * args.steps / el
     iters = [r["iterations"] for r in reps]
-    ref = stepper.sequential(p, u0_h)
-    err = stepper.rel_err(U.cpu().numpy(), ref)
+    if name in ORACLE_IN_BENCH:
+        ref = stepper.sequential(p, u0_h)
+        err = stepper.rel_err(U.cpu().numpy(), ref)
+    else:
+        ref, err = None, None
+        s_chk = Solver.for_problem(p, precision=args.precision, device=dev)
+        m, e = s_chk.diagnostics(U)
+        m, e = m.cpu().numpy(), e.cpu().numpy()
+        invariants = {"mass_drift_max": float(np.max(np.abs(m - m[0]))),
+                      "energy_nonincreasing": bool(np.all(np.diff(e) <= 1e-13 * np.abs(e[1:]))),
+                      "energy_first_last": [float(e[0]), float(e[-1])]}
+        del s_chk
     log(f"{name} {args.precision}: {args.steps} solves in {el:.3f}s, iterations {sorted(set(iters))}, "
-        f"rel err vs oracle {err:.2e}, update history {['%.1e' % x for x in reps[-1]['upd_hist']]}, "
+        f"rel err vs oracle {err if err is None else f'{err:.2e}'}, update history {['%.1e' % x for x in reps[-1]['upd_hist']]}, "
         f"estimate {reps[-1]['est_rel_err']:.1e}")
     # the same K solves again with HIP events recorded on the solve's stream
     # around every kernel launch (per-kernel durations; events add overhead,
@@ -347,6 +366,7 @@ def main():
                    "dof": p.dof, "alpha": reps[-1]["alpha"], "rtol": 1e-10,
                    "iterations": iters[-1]},
         "rel_err_vs_oracle": err,
+        **({} if ref is not None else {"invariants": invariants}),
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "roofline": roofline,
@@ -360,15 +380,18 @@ def main():
         # variants get a second loop with events for the contraction kernel)
         out["paths"] = {}
         variants = [(o, "fft", None) for o in ("mixed", "fp32", "fp64") if o != args.precision]
-        variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", BF16_ALPHA),
-                     ("bf16", "dense", BF16_ALPHA)]
+        # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
+        bf16_alpha = 4e-3 if name == "c5" else BF16_ALPHA
+        variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", bf16_alpha),
+                     ("bf16", "dense", bf16_alpha)]
         for prec, tp, al in variants:
             key = prec if tp == "fft" else f"{prec}_dense"
             elo, _, repso, Uo = run(prec, args.steps, args.warmup, False, tp, al)
             log(f"{key} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
             d = {"value": p.dof * args.steps / elo, "ms_per_step": elo / args.steps * 1e3,
                  "iterations": repso[-1]["iterations"], "alpha": repso[-1]["alpha"],
-                 "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref)}
+                 "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref) if ref is not None else None,
+                 "rel_diff_vs_headline": stepper.rel_err(Uo.cpu().numpy(), U.cpu().numpy())}
             if tp == "dense":
                 _, _, repe, _ = run(prec, args.steps, args.warmup, True, tp, al)
                 its = sum(r["iterations"] for r in repe)

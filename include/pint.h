@@ -249,6 +249,9 @@ typedef struct pint_server_config {
   size_t pool_bytes;    /* >= 4096                                              */
   int max_active;       /* requests in flight at once (HIP streams); 1..64, 0 = 8 */
   unsigned flags;       /* PINT_SERVER_*                                        */
+  size_t host_pool_bytes; /* pinned host memory for finished results of
+                             host-buffer requests awaiting pint_server_wait;
+                             0 = 1 GiB.  Allocated by the server.             */
 } pint_server_config;
 
 typedef struct pint_server_statistics {
@@ -263,13 +266,16 @@ typedef struct pint_server_statistics {
   uint64_t graphs_captured, graph_updates, graph_launches;
   double worker_host_seconds;  /* worker thread time spent admitting requests and
                                   enqueueing their iterations                  */
+  size_t host_pool_bytes, host_pool_in_use;  /* pinned result pool            */
 } pint_server_statistics;
 
 /* Start a server on the current device; *out receives it.  The pool stays
- * owned by the caller and must outlive the server.  A finished request
- * submitted with host buffers keeps its block of the pool (its U stays in
- * HBM) until pint_server_wait copies U out, so results that are never
- * collected keep their memory until the server is destroyed. */
+ * owned by the caller and must outlive the server.  A host-buffer request is
+ * admitted only when its result also fits in the pinned host result pool;
+ * its U is copied there when it finishes (freeing its device block) and stays
+ * until pint_server_wait copies it out, so results that are never collected
+ * hold pinned memory until the server is destroyed.  Every HIP call of the
+ * server is made on its worker thread. */
 int pint_server_create(const pint_server_config* cfg, pint_server** out);
 /* Validate and enqueue one solve (u0 broadcast as the initial guess);
  * h_u0 ([N_y][N_x] FP64 host) is copied, so the caller may reuse it at once.

@@ -63,7 +63,7 @@ class Report(ct.Structure):
 class ServerConfig(ct.Structure):
     _fields_ = [
         ("struct_size", ct.c_size_t), ("d_pool", ct.c_void_p), ("pool_bytes", ct.c_size_t),
-        ("max_active", ct.c_int), ("flags", ct.c_uint),
+        ("max_active", ct.c_int), ("flags", ct.c_uint), ("host_pool_bytes", ct.c_size_t),
     ]
 
 
@@ -77,6 +77,7 @@ class ServerStats(ct.Structure):
         ("dof_completed", ct.c_double), ("busy_seconds", ct.c_double),
         ("graphs_captured", ct.c_uint64), ("graph_updates", ct.c_uint64), ("graph_launches", ct.c_uint64),
         ("worker_host_seconds", ct.c_double),
+        ("host_pool_bytes", ct.c_size_t), ("host_pool_in_use", ct.c_size_t),
     ]
 
 

@@ -24,6 +24,8 @@
 #include "pint_kernels.hpp"
 #include "fft_lds.hpp"
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 namespace pint {
@@ -90,7 +92,14 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     table_to_lds<T, NT, N>(s_wq, dt.wq);
   }
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs round-robin.  With the remap, XCD x
+  // runs the contiguous range of logical blocks [x B/8, (x+1) B/8) in order
+  // (B blocks in the grid),
+  // so the halo rows shared by adjacent row blocks and the level n-1 rows
+  // read again by level n are fetched into the same L2.
+  const int nblk = gridDim.x;
+  const int b = (a.xcd_remap && (nblk & 7) == 0) ? int(blockIdx.x & 7) * (nblk >> 3) + int(blockIdx.x >> 3)
+                                                  : int(blockIdx.x);
   const int lev = DIM == 2 ? b / NBL : b * RB;
   const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
@@ -592,8 +601,9 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
       dsq += pp[PART_DSQ];
       usq += pp[PART_USQ];
       u2 += pp[PART_U2];
-      rsq += pp[PART_RSQ];
     }
+    // the forward pass has its own block grid (same slots, its own field)
+    for (int bb = 0; bb < f.nbl_f; ++bb) rsq += f.part[(size_t(n) * f.nbl_f + bb) * PART_STRIDE + PART_RSQ];
     v[0] = (dsq != dsq || dsq > v[0]) ? dsq : v[0];
     v[1] = (usq != usq || usq > v[1]) ? usq : v[1];
     v[2] += u2;
@@ -762,6 +772,23 @@ struct row_cfg {
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
+// The forward pass holds v (RB + 4 rows), g (RB + 2 rows) and the FFT buffer
+// in LDS, FP64: for N >= 128 it takes half the rows of the inverse pass so
+// that two to three blocks fit per CU and their phases overlap.
+template <int DIM, int N, bool WIDE>
+struct row_fwd_cfg {
+  static constexpr int RB = (DIM == 2 && N >= 128 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
+  static constexpr int NT = RB * N < 256 ? RB * N : 256;
+  static constexpr int NBL = DIM == 2 ? N / RB : 1;
+};
+// Tuning switch: PINT_ROWS_FWD=wide selects the inverse pass's block height.
+static bool rows_fwd_wide() {
+  static const bool wide = [] {
+    const char* s = std::getenv("PINT_ROWS_FWD");
+    return s && std::strcmp(s, "wide") == 0;
+  }();
+  return wide;
+}
 // Column-pass tile width and threads.
 template <int N>
 struct col_cfg {
@@ -783,15 +810,30 @@ int rows_blocks_per_level(int dim, int n) {
   }
 }
 
+int rows_fwd_blocks_per_level(int dim, int n) {
+  if (dim != 2) return 1;
+  const bool w = rows_fwd_wide();
+  switch (n) {
+    case 8: return row_fwd_cfg<2, 8, false>::NBL;
+    case 16: return row_fwd_cfg<2, 16, false>::NBL;
+    case 32: return row_fwd_cfg<2, 32, false>::NBL;
+    case 64: return row_fwd_cfg<2, 64, false>::NBL;
+    case 128: return w ? row_fwd_cfg<2, 128, true>::NBL : row_fwd_cfg<2, 128, false>::NBL;
+    case 256: return w ? row_fwd_cfg<2, 256, true>::NBL : row_fwd_cfg<2, 256, false>::NBL;
+    case 512: return w ? row_fwd_cfg<2, 512, true>::NBL : row_fwd_cfg<2, 512, false>::NBL;
+    default: return 0;
+  }
+}
+
 int rows_levels_per_block(int dim, int n) {
   (void)n;
   return dim == 1 ? row_cfg<1, 8>::RB : 1;
 }
 
-template <typename T, typename TO, int DIM, int N>
-static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+template <typename T, typename TO, int DIM, int N, bool WIDE>
+static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
-  using C = row_cfg<DIM, N>;
+  using C = row_fwd_cfg<DIM, N, WIDE>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
     hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, rout,
@@ -801,6 +843,13 @@ static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, con
                        dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+template <typename T, typename TO, int DIM, int N>
+static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+                                    int mode, hipStream_t st) {
+  if (DIM == 2 && N >= 128 && rows_fwd_wide()) return launch_rows_fwd_w<T, TO, DIM, N, true>(a, S, rout, dt, nt, mode, st);
+  return launch_rows_fwd_w<T, TO, DIM, N, false>(a, S, rout, dt, nt, mode, st);
 }
 
 template <typename T, int DIM, int N>
@@ -924,9 +973,11 @@ hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& d
 template <typename T, int NTT>
 struct time_cfg {
   static constexpr int BYTES = NTT * int(sizeof(cx<T>));  // one complex column
-  static constexpr int CMAX0 = 65536 / BYTES;
+  // default tile within 64 KB of LDS; up to 128 KB on request (gfx950 has 160 KB)
+  static constexpr int CDEF0 = 65536 / BYTES, CMAX0 = 131072 / BYTES;
   static constexpr int MMAX = 2 * (CMAX0 < 32 ? CMAX0 : 32);
-  static constexpr int MDEF = MMAX < 32 ? MMAX : 32;
+  static constexpr int MDEF0 = 2 * (CDEF0 < 32 ? CDEF0 : 32);
+  static constexpr int MDEF = MDEF0 < 32 ? MDEF0 : 32;
 };
 
 template <typename T, int NTT, int M>

@@ -43,6 +43,7 @@ struct pint_plan {
   double h, alpha, a, dof, rtol;
   int max_iter;
   int nbl;          // row blocks per level (2D), 1 in 1D
+  int nbl_f;        // blocks per level of the forward (residual) row pass
   int predict = 2;  // iterations enqueued before the first stop-flag check
   double safety = 0.1;
   bool fp64;   // working precision W = double
@@ -387,7 +388,8 @@ struct Work {
 // Partial-result slots: one per [level][row block]; the initial c_bar
 // reduction needs one per 4096 values of the initial guess.
 size_t part_bytes(const pint_plan* pl) {
-  const size_t slots = std::max<size_t>((size_t)pl->nt * pl->nbl, ((size_t)pl->nt * pl->ns + 4095) / 4096);
+  const size_t slots = std::max<size_t>((size_t)pl->nt * std::max(pl->nbl, pl->nbl_f),
+                                        ((size_t)pl->nt * pl->ns + 4095) / 4096);
   return align256(slots * PART_STRIDE * 8);
 }
 size_t s_bytes(const pint_plan* pl) { return align256((size_t)pl->nt * pl->ns * (pl->fp64 ? 8 : 4)); }
@@ -465,7 +467,7 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.part = w.part;
   ra.done = &w.ctrl->done;
   ra.bcast = bcast ? 1 : 0;
-  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->dof, pl->rtol, pl->safety};
+  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->dof, pl->rtol, pl->safety};
   UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0};
   T* S = static_cast<T*>(w.S);
   TF* SF = std::is_same<TF, T>::value ? reinterpret_cast<TF*>(w.S) : static_cast<TF*>(w.S64);
@@ -575,6 +577,7 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   pl->mixed = p->precision == PINT_PREC_MIXED || p->precision == PINT_PREC_BF16_REFINE;
   pl->dense = dense_kind_of(p);
   pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
+  pl->nbl_f = rows_fwd_blocks_per_level(pl->dim, pl->n);
   if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {
     delete pl;
     return set_err(nullptr, PINT_EINVAL, "nt must be a multiple of the 1D levels per block");
@@ -611,6 +614,9 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
 
   // residual coefficients
   ResidArgs& ra = pl->ra;
+  // tuning switch: PINT_XCD_REMAP=0 keeps the hardware's block order
+  const char* remap = std::getenv("PINT_XCD_REMAP");
+  ra.xcd_remap = (remap && std::strcmp(remap, "0") == 0) ? 0 : 1;
   ra.inv_dt = 1.0 / p->dt;
   ra.inv_h2 = 1.0 / (pl->h * pl->h);
   ra.theta = pl->p.theta;

@@ -44,6 +44,7 @@ struct ResidArgs {
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
   int bcast;        // the iterate is u0 at every level (first iteration)
+  int xcd_remap;    // order blocks so that neighbours share an XCD's L2
 };
 
 struct FinArgs {
@@ -51,6 +52,7 @@ struct FinArgs {
   Ctrl* host;  // pinned host mirror of the status fields (nullable)
   const double* part;
   int nt, nbl, max_iter;
+  int nbl_f;  // blocks per level of the forward row pass (its residual partials)
   double dof, rtol, safety;
 };
 
@@ -104,6 +106,9 @@ struct DiagArgs {
 // Row blocks per level of the 2D row passes (1 in 1D), and levels per block
 // of the 1D row passes (1 in 2D).
 int rows_blocks_per_level(int dim, int n);
+// Blocks per level of the forward (residual) row pass, which may use narrower
+// blocks than the inverse pass.
+int rows_fwd_blocks_per_level(int dim, int n);
 int rows_levels_per_block(int dim, int n);
 
 // Forward row pass computing in T, storing the x-DCT in TO.

@@ -9,7 +9,12 @@
 // sub-allocation of the caller's pool (first-fit, coalescing free list).  A
 // request is admitted only when its whole footprint fits, so the server never
 // allocates device memory itself and never calls hipFree while work runs.
-// Host staging buffers per slot are pinned (hipHostMalloc) and reused.
+// Results of host-buffer requests go to a pinned host result pool allocated
+// once at creation, where they wait for pint_server_wait.
+//
+// Threads: every HIP call of a server is made by its worker thread (besides
+// creation and destruction).  Client threads only validate, queue, and copy
+// finished results out of pinned host memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,8 +48,8 @@ struct Req {
   pint_problem prob{};
   pint_plan* plan = nullptr;
   std::vector<double> u0;
-  bool held = false;             // finished; U still in the pool block for wait
-  double* d_res = nullptr;       // where (pool block of a host-buffer request)
+  size_t h_off = 0;              // pinned result block (host-buffer requests)
+  bool h_held = false;           // the block holds the finished U until wait
   const double* d_u0 = nullptr;  // caller-owned device input (device-resident requests)
   double* d_U = nullptr;         // caller-owned device state and result
   pint_report rep{};
@@ -59,7 +64,7 @@ struct Req {
   Clock::time_point t_submit, t_admit, t_done;
 };
 
-enum SlotState { SL_IDLE, SL_RUNNING };
+enum SlotState { SL_IDLE, SL_RUNNING, SL_DRAINING };
 
 using ShapeKey = std::tuple<int, int, int, int, unsigned>;  // dim, n, nt, precision, flags
 
@@ -133,6 +138,8 @@ struct pint_server {
   int device = 0;
   unsigned char* pool = nullptr;
   PoolAlloc alloc;
+  unsigned char* h_pool = nullptr;  // pinned host result pool
+  PoolAlloc h_alloc;
   std::vector<Slot> slots;
   std::deque<Req*> queue;
   std::map<uint64_t, Req*> reqs;
@@ -303,36 +310,44 @@ int start_req(pint_server* s, Slot& sl, Req* r) {
   return PINT_OK;
 }
 
-// Advance a slot whose last event completed: retire its request if it has
-// stopped, else enqueue one more iteration.  Lock held.  A retired
-// host-buffer request keeps its pool block (U stays in HBM) until
-// pint_server_wait copies U out on the caller's thread.
+// Advance a slot whose last event completed.  Running: retire the request
+// if it has stopped (a host-buffer request first copies U into its pinned
+// result block and drains), else enqueue one more iteration.  Draining: the
+// copy is done; release the device block.  Lock held.
 int advance(pint_server* s, Slot& sl) {
   Req* r = sl.req;
-  const Ctrl& c = *sl.h_ctrl;
-  const bool done = reinterpret_cast<const volatile int&>(c.done) != 0;
-  const int maxit = plan_max_iter(r->plan);
-  if (!(r->cancel || done || sl.it_enq >= maxit)) {
-    int rc = enqueue_it(s, sl, sl.it_enq);
-    if (rc) return rc;
-    ++sl.it_enq;
-    if (hipEventRecord(sl.ev, sl.st) != hipSuccess) return srv_fail(s, PINT_EHIP, "hipEventRecord failed");
-    return PINT_OK;
+  if (sl.state == SL_RUNNING) {
+    const Ctrl& c = *sl.h_ctrl;
+    const bool done = reinterpret_cast<const volatile int&>(c.done) != 0;
+    const int maxit = plan_max_iter(r->plan);
+    if (!(r->cancel || done || sl.it_enq >= maxit)) {
+      int rc = enqueue_it(s, sl, sl.it_enq);
+      if (rc) return rc;
+      ++sl.it_enq;
+      if (hipEventRecord(sl.ev, sl.st) != hipSuccess) return srv_fail(s, PINT_EHIP, "hipEventRecord failed");
+      return PINT_OK;
+    }
+    // every enqueued iteration has finished (the slot's event completed)
+    r->status = r->cancel ? PINT_ECANCELED : solve_status(r->plan, c, &r->rep);
+    if (r->status == PINT_OK) s->predict[sl.cur_key] = c.iter;
+    sl.state = SL_DRAINING;
+    if (!r->cancel && !r->d_U) {
+      void* dst = s->h_pool + r->h_off;
+      if (hipMemcpyAsync(dst, sl.d_U, r->ns * r->nt * sizeof(double), hipMemcpyDeviceToHost, sl.st) != hipSuccess)
+        return srv_fail(s, PINT_EHIP, "result copy failed");
+      if (hipEventRecord(sl.ev, sl.st) != hipSuccess) return srv_fail(s, PINT_EHIP, "hipEventRecord failed");
+      r->h_held = true;
+      return PINT_OK;
+    }
   }
-  // every enqueued iteration has finished (the slot's event completed)
-  const int status = r->cancel ? PINT_ECANCELED : solve_status(r->plan, c, &r->rep);
-  if (status == PINT_OK) s->predict[sl.cur_key] = c.iter;
+  // draining (or nothing to copy): release the device block and retire
   r->rep.struct_size = sizeof(pint_report);
   r->rep.ms_total = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
-  if (!r->cancel && !r->d_U) {
-    r->held = true;
-    r->d_res = sl.d_U;
-  } else {
-    s->alloc.release(r->pool_off, r->footprint);
-  }
+  s->alloc.release(r->pool_off, r->footprint);
+  if (!r->h_held && !r->d_U) s->h_alloc.release(r->h_off, r->ns * r->nt * sizeof(double));
   sl.req = nullptr;
   sl.state = SL_IDLE;
-  finish_req(s, r, status);
+  finish_req(s, r, r->status);
   return PINT_OK;
 }
 
@@ -357,10 +372,16 @@ void worker_main(pint_server* s) {
           break;
         }
       if (!free_slot) break;
-      size_t off = 0;
-      if (!s->alloc.alloc(r->footprint, &off)) break;
+      size_t off = 0, hoff = 0;
+      const size_t hbytes = r->d_U ? 0 : r->ns * r->nt * sizeof(double);
+      if (hbytes && !s->h_alloc.alloc(hbytes, &hoff)) break;
+      if (!s->alloc.alloc(r->footprint, &off)) {
+        if (hbytes) s->h_alloc.release(hoff, hbytes);
+        break;
+      }
       s->queue.pop_front();
       r->pool_off = off;
+      r->h_off = hoff;
       s->pool_peak = std::max(s->pool_peak, s->alloc.used());
       const Clock::time_point h0 = Clock::now();
       g_srv_err.clear();
@@ -369,6 +390,7 @@ void worker_main(pint_server* s) {
       if (rc) {
         (void)hipStreamSynchronize(free_slot->st);  // pending copies read the plan's host tables
         s->alloc.release(off, r->footprint);
+        if (hbytes) s->h_alloc.release(hoff, hbytes);
         free_slot->req = nullptr;
         free_slot->state = SL_IDLE;
         finish_req(s, r, rc);
@@ -392,6 +414,8 @@ void worker_main(pint_server* s) {
         (void)hipStreamSynchronize(sl.st);
         if (r) {
           s->alloc.release(r->pool_off, r->footprint);
+          if (!r->d_U) s->h_alloc.release(r->h_off, r->ns * r->nt * sizeof(double));
+          r->h_held = false;
           finish_req(s, r, rc);
         }
         sl.req = nullptr;
@@ -457,6 +481,11 @@ int submit_common(pint_server* s, const pint_problem* p, const double* h_u0, con
     delete r;
     return srv_fail(s, PINT_ENOMEM, "request footprint exceeds the whole pool");
   }
+  if (!d_U && r->ns * r->nt * sizeof(double) > s->h_alloc.size()) {
+    pint_plan_destroy(plan);
+    delete r;
+    return srv_fail(s, PINT_ENOMEM, "result exceeds the whole pinned host result pool");
+  }
   if (h_u0) r->u0.assign(h_u0, h_u0 + r->ns);
   r->t_submit = t_submit;
   {
@@ -495,6 +524,12 @@ int pint_server_create(const pint_server_config* cfg, pint_server** out) {
   (void)hipGetDevice(&s->device);
   s->pool = static_cast<unsigned char*>(cfg->d_pool);
   s->alloc.reset(cfg->pool_bytes & ~size_t(255));
+  const size_t hbytes = cfg->host_pool_bytes ? cfg->host_pool_bytes : (size_t(1) << 30);
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->h_pool), hbytes, hipHostMallocDefault) != hipSuccess) {
+    delete s;
+    return srv_fail(nullptr, PINT_ENOMEM, "pinned host result pool allocation failed");
+  }
+  s->h_alloc.reset(hbytes & ~size_t(255));
   s->slots.resize(nslots);
   for (auto& sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
@@ -538,22 +573,15 @@ int pint_server_wait(pint_server* s, uint64_t ticket, double* h_U, pint_report* 
     r->waited = false;
     return srv_fail(s, PINT_ETIMEDOUT, "timed out");
   }
-  int status = r->status;
+  const int status = r->status;
   s->reqs.erase(it);  // the request is ours now: copy out without holding the lock
   lk.unlock();
-  if (r->held) {
-    if (h_U) {
-      int prev = 0;
-      (void)hipGetDevice(&prev);
-      (void)hipSetDevice(s->device);
-      const hipError_t e = hipMemcpy(h_U, r->d_res, r->ns * r->nt * sizeof(double), hipMemcpyDeviceToHost);
-      (void)hipSetDevice(prev);
-      if (e != hipSuccess) status = srv_fail(s, PINT_EHIP, std::string("result copy: ") + hipGetErrorString(e));
-    }
+  if (r->h_held) {
+    if (h_U) std::memcpy(h_U, s->h_pool + r->h_off, r->ns * r->nt * sizeof(double));
     lk.lock();
-    s->alloc.release(r->pool_off, r->footprint);
+    s->h_alloc.release(r->h_off, r->ns * r->nt * sizeof(double));
     lk.unlock();
-    s->cv_work.notify_one();  // freed pool memory may admit a queued request
+    s->cv_work.notify_one();  // freed result memory may admit a queued request
   }
   if (!r->err.empty() && status == r->status) g_srv_err = r->err;
   if (rep) {
@@ -614,6 +642,8 @@ int pint_server_stats(pint_server* s, pint_server_statistics* st) {
   st->graph_updates = s->graph_updates;
   st->graph_launches = s->graph_launches;
   st->worker_host_seconds = s->host_seconds;
+  st->host_pool_bytes = s->h_alloc.size();
+  st->host_pool_in_use = s->h_alloc.used();
   return PINT_OK;
 }
 
@@ -640,6 +670,7 @@ int pint_server_destroy(pint_server* s) {
     if (kv.second->plan) pint_plan_destroy(kv.second->plan);
     delete kv.second;
   }
+  if (s->h_pool) (void)hipHostFree(s->h_pool);
   delete s;
   return PINT_OK;
 }

@@ -13,11 +13,12 @@ from . import _pint
 
 
 class Server:
-    """A running server with a device pool of ``pool_bytes`` and up to
-    ``max_active`` requests in flight."""
+    """A running server with a device pool of ``pool_bytes``, up to
+    ``max_active`` requests in flight, and a pinned host pool of
+    ``host_pool_bytes`` (0: 1 GiB) for results of host-buffer requests."""
 
     def __init__(self, pool_bytes: int, max_active: int = 8, graphs: bool = True, device=None,
-                 library: _pint.Lib | None = None):
+                 library: _pint.Lib | None = None, host_pool_bytes: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the server needs a ROCm GPU")
         self.lib = library or _pint.lib()
@@ -31,6 +32,7 @@ class Server:
             cfg.pool_bytes = pool_bytes
             cfg.max_active = max_active
             cfg.flags = 0 if graphs else _pint.SERVER_NO_GRAPHS
+            cfg.host_pool_bytes = host_pool_bytes
             h = ct.c_void_p()
             self._check(self.lib.dll.pint_server_create(ct.byref(cfg), ct.byref(h)), None)
         self.h = h
