@@ -92,14 +92,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     table_to_lds<T, NT, N>(s_wq, dt.wq);
   }
   const int tid = threadIdx.x;
-  // Workgroups are dealt to the 8 XCDs round-robin.  With the remap, XCD x
-  // runs the contiguous range of logical blocks [x B/8, (x+1) B/8) in order
-  // (B blocks in the grid),
-  // so the halo rows shared by adjacent row blocks and the level n-1 rows
-  // read again by level n are fetched into the same L2.
-  const int nblk = gridDim.x;
-  const int b = (a.xcd_remap && (nblk & 7) == 0) ? int(blockIdx.x & 7) * (nblk >> 3) + int(blockIdx.x >> 3)
-                                                  : int(blockIdx.x);
+  const int b = blockIdx.x;
   const int lev = DIM == 2 ? b / NBL : b * RB;
   const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
@@ -126,7 +119,8 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
           hn[i] = hm[i] = a.u0[off];
         } else {
           hn[i] = a.U[lev * ns + off];
-          hm[i] = lev == 0 ? a.u0[off] : a.U[(lev - 1) * ns + off];
+          // v = theta u_n + (1 - theta) u_{n-1}: no u_{n-1} halo for theta = 1
+          if (omth != 0.0) hm[i] = lev == 0 ? a.u0[off] : a.U[(lev - 1) * ns + off];
         }
       }
     }
@@ -773,11 +767,12 @@ struct row_cfg {
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
 // The forward pass holds v (RB + 4 rows), g (RB + 2 rows) and the FFT buffer
-// in LDS, FP64: for N >= 128 it takes half the rows of the inverse pass so
-// that two to three blocks fit per CU and their phases overlap.
+// in LDS, FP64: for N >= 256 it takes half the rows of the inverse pass so
+// that two to three blocks fit per CU and their phases overlap (measured:
+// -35% at 256^2; at 128^2 the taller block is as fast).
 template <int DIM, int N, bool WIDE>
 struct row_fwd_cfg {
-  static constexpr int RB = (DIM == 2 && N >= 128 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
+  static constexpr int RB = (DIM == 2 && N >= 256 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
   static constexpr int NT = RB * N < 256 ? RB * N : 256;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
@@ -818,7 +813,7 @@ int rows_fwd_blocks_per_level(int dim, int n) {
     case 16: return row_fwd_cfg<2, 16, false>::NBL;
     case 32: return row_fwd_cfg<2, 32, false>::NBL;
     case 64: return row_fwd_cfg<2, 64, false>::NBL;
-    case 128: return w ? row_fwd_cfg<2, 128, true>::NBL : row_fwd_cfg<2, 128, false>::NBL;
+    case 128: return row_fwd_cfg<2, 128, false>::NBL;
     case 256: return w ? row_fwd_cfg<2, 256, true>::NBL : row_fwd_cfg<2, 256, false>::NBL;
     case 512: return w ? row_fwd_cfg<2, 512, true>::NBL : row_fwd_cfg<2, 512, false>::NBL;
     default: return 0;
@@ -848,7 +843,7 @@ static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, con
 template <typename T, typename TO, int DIM, int N>
 static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
-  if (DIM == 2 && N >= 128 && rows_fwd_wide()) return launch_rows_fwd_w<T, TO, DIM, N, true>(a, S, rout, dt, nt, mode, st);
+  if (DIM == 2 && N >= 256 && rows_fwd_wide()) return launch_rows_fwd_w<T, TO, DIM, N, true>(a, S, rout, dt, nt, mode, st);
   return launch_rows_fwd_w<T, TO, DIM, N, false>(a, S, rout, dt, nt, mode, st);
 }
 
@@ -973,11 +968,13 @@ hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& d
 template <typename T, int NTT>
 struct time_cfg {
   static constexpr int BYTES = NTT * int(sizeof(cx<T>));  // one complex column
-  // default tile within 64 KB of LDS; up to 128 KB on request (gfx950 has 160 KB)
-  static constexpr int CDEF0 = 65536 / BYTES, CMAX0 = 131072 / BYTES;
+  // Default tile: the modes whose columns fit in 32 KB of LDS, in [8, 32], so
+  // that several blocks share a CU (measured at N_t = 1024: 8 modes 1.5 ms,
+  // 16 modes 2.1 ms, 32 modes 3.2 ms per launch); up to 128 KB on request.
+  static constexpr int CDEF0 = 32768 / BYTES, CMAX0 = 131072 / BYTES;
   static constexpr int MMAX = 2 * (CMAX0 < 32 ? CMAX0 : 32);
   static constexpr int MDEF0 = 2 * (CDEF0 < 32 ? CDEF0 : 32);
-  static constexpr int MDEF = MDEF0 < 32 ? MDEF0 : 32;
+  static constexpr int MDEF = MDEF0 < 8 ? 8 : (MDEF0 < 32 ? MDEF0 : 32);
 };
 
 template <typename T, int NTT, int M>

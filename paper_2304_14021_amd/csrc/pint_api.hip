@@ -614,9 +614,6 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
 
   // residual coefficients
   ResidArgs& ra = pl->ra;
-  // tuning switch: PINT_XCD_REMAP=0 keeps the hardware's block order
-  const char* remap = std::getenv("PINT_XCD_REMAP");
-  ra.xcd_remap = (remap && std::strcmp(remap, "0") == 0) ? 0 : 1;
   ra.inv_dt = 1.0 / p->dt;
   ra.inv_h2 = 1.0 / (pl->h * pl->h);
   ra.theta = pl->p.theta;

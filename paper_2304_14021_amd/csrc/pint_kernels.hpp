@@ -44,7 +44,6 @@ struct ResidArgs {
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
   int bcast;        // the iterate is u0 at every level (first iteration)
-  int xcd_remap;    // order blocks so that neighbours share an XCD's L2
 };
 
 struct FinArgs {
