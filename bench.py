@@ -26,6 +26,11 @@ METRIC = "space-time DOF/s at 1e-10 rel err vs FP64 oracle; p50/p99 solve latenc
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # dense, MI355X
 BF16_ALPHA = 1e-2  # alpha of the BF16 runs (coarser contraction, larger alpha)
+# HBM bytes per launch of the dominant kernel from two rocprofv3 counter passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives),
+# profiles/c2_mixed_hbm_traffic.md.  Valid for the kernel as measured: drop the
+# entry when that kernel changes.
+MEASURED_TRAFFIC = {("c2", "mixed", "rows_fwd"): (11578.8 * 2.0 + 16400.0) * 1024}
 PREC_DESC = {
     "mixed": "FP64 residual, FP64 forward DCT, FP32 time FFT solve and inverse DCT, FP64 update "
              "(iterative refinement)",
@@ -341,8 +346,10 @@ def main():
     kern_fin_us = avg_ms["finalize"] * 1e3
     dom = max(steady, key=lambda k: avg_ms[k])
     ach = kern[dom]["gbs"]
+    traffic = MEASURED_TRAFFIC.get((name, args.precision, dom))
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS if ach else None, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS if ach else None,
+                "traffic": traffic / 1e9 if traffic is not None else None, "traffic_unit": "GB per launch",
                 "kernel": KERNEL_NAMES[dom], "algo_bytes_per_launch": kern[dom]["algo_bytes"],
                 "avg_launch_us": kern[dom]["avg_us"]}
     log("kernels: " + json.dumps(kern))

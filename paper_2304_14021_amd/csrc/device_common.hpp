@@ -80,4 +80,36 @@ __device__ __forceinline__ void block_reduce(double* scratch, double (&v)[NV], c
   __syncthreads();
 }
 
+// Same contract as block_reduce (fixed combination order, NaN-propagating
+// max), in two levels: an xor-shuffle tree inside each wave, then wave 0
+// combines the per-wave results from LDS.  One barrier instead of log2(NT).
+// The result is valid in thread 0.  scratch: NV * (NT / 64) doubles.
+template <int NT, int NV>
+__device__ __forceinline__ void block_reduce_waves(double* scratch, double (&v)[NV], const bool (&is_max)[NV]) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double b = __shfl_xor(v[q], off, 64);
+      v[q] = is_max[q] ? ((v[q] != v[q] || v[q] > b) ? v[q] : b) : v[q] + b;
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) scratch[q * NW + wave] = v[q];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = lane < NW ? scratch[q * NW + lane] : 0.0;  // values are >= 0
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double b = __shfl_xor(v[q], off, 64);
+        v[q] = is_max[q] ? ((v[q] != v[q] || v[q] > b) ? v[q] : b) : v[q] + b;
+      }
+  }
+}
+
 }  // namespace pint

@@ -585,31 +585,71 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
 // stop when est <= safety * rtol (k >= 2, rho < 1) or rel <= 1e-3 rtol;
 // diverged on NaN/Inf or when the update grows 1e3-fold over the first one.
 // The scalar averaged Jacobian for the next time solve is mean(3 u^2).
+// Per-level sums: a group of g lanes (g = the power of two >= the blocks per
+// level, at most 64) reads one level's block partials together, several
+// levels per wave and FL levels per lane in flight, and combines them with a
+// fixed xor-shuffle tree, so every sum is formed in the same order each run.
+// Control-record fields the stop rule reads, loaded by thread 0 before the
+// reduction so that their latency overlaps it.
+struct CtrlPrev {
+  int iter;
+  double upd_prev, upd_first;
+};
+
 template <int NT>
 __device__ void finalize_body(const FinArgs& f, double* red) {
-  double v[4] = {0.0, 0.0, 0.0, 0.0};  // max dsq, max usq, sum u2, max rsq
-  for (int n = threadIdx.x; n < f.nt; n += NT) {
-    double dsq = 0.0, usq = 0.0, u2 = 0.0, rsq = 0.0;
-    for (int bb = 0; bb < f.nbl; ++bb) {
-      const double* pp = f.part + (size_t(n) * f.nbl + bb) * PART_STRIDE;
-      dsq += pp[PART_DSQ];
-      usq += pp[PART_USQ];
-      u2 += pp[PART_U2];
+  CtrlPrev c0{0, 0.0, 0.0};
+  if (threadIdx.x == 0) {
+    c0.iter = f.ctrl->iter;
+    c0.upd_prev = f.ctrl->upd_prev;
+    c0.upd_first = f.ctrl->upd_first;
+  }
+  constexpr int NW = NT / 64, FL = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
+  int g = 1;
+  while (g < gmax && g < 64) g <<= 1;
+  const int lpw = 64 / g;  // levels per wave per step
+  const int sub = lane / g, j = lane - (lane / g) * g;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // max dsq, max usq, sum u2, max rsq (group leaders)
+  for (int base = wave * lpw; base < f.nt; base += NW * lpw * FL) {
+    double s[FL][4];
+#pragma unroll
+    for (int u = 0; u < FL; ++u) {
+      const int n = base + u * NW * lpw + sub;
+      s[u][0] = s[u][1] = s[u][2] = s[u][3] = 0.0;
+      if (n < f.nt) {
+        for (int bb = j; bb < f.nbl; bb += g) {
+          const double* pp = f.part + (size_t(n) * f.nbl + bb) * PART_STRIDE;
+          s[u][0] += pp[PART_DSQ];
+          s[u][1] += pp[PART_USQ];
+          s[u][2] += pp[PART_U2];
+        }
+        // the forward pass has its own block grid (same slots, its own field)
+        for (int bb = j; bb < f.nbl_f; bb += g) s[u][3] += f.part[(size_t(n) * f.nbl_f + bb) * PART_STRIDE + PART_RSQ];
+      }
     }
-    // the forward pass has its own block grid (same slots, its own field)
-    for (int bb = 0; bb < f.nbl_f; ++bb) rsq += f.part[(size_t(n) * f.nbl_f + bb) * PART_STRIDE + PART_RSQ];
-    v[0] = (dsq != dsq || dsq > v[0]) ? dsq : v[0];
-    v[1] = (usq != usq || usq > v[1]) ? usq : v[1];
-    v[2] += u2;
-    v[3] = (rsq != rsq || rsq > v[3]) ? rsq : v[3];
+#pragma unroll
+    for (int u = 0; u < FL; ++u) {
+      for (int off = g >> 1; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[u][q] += __shfl_xor(s[u][q], off, 64);
+      const int n = base + u * NW * lpw + sub;
+      if (j == 0 && n < f.nt) {
+        v[0] = (s[u][0] != s[u][0] || s[u][0] > v[0]) ? s[u][0] : v[0];
+        v[1] = (s[u][1] != s[u][1] || s[u][1] > v[1]) ? s[u][1] : v[1];
+        v[2] += s[u][2];
+        v[3] = (s[u][3] != s[u][3] || s[u][3] > v[3]) ? s[u][3] : v[3];
+      }
+    }
   }
   const bool ismax[4] = {true, true, false, true};
-  block_reduce<NT, 4>(red, v, ismax);
+  block_reduce_waves<NT, 4>(red, v, ismax);
   if (threadIdx.x != 0) return;
   Ctrl* c = f.ctrl;
   const double upd = sqrt(v[0]), unrm = sqrt(v[1]), res = sqrt(v[3]);
   const double cbar = v[2] / f.dof;
-  const int k = c->iter;  // 0-based index of the iteration just finished
+  const int k = c0.iter;  // 0-based index of the iteration just finished
   const double rel = unrm > 0.0 ? upd / unrm : upd;
   if (k < PINT_HIST_DEV) {
     c->upd_hist[k] = rel;
@@ -619,15 +659,16 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
   c->c_bar = cbar;
   const bool bad = !(upd == upd) || !(unrm == unrm) || !(cbar == cbar) || upd > 1e300 || unrm > 1e300;
   double est = 1e300;
-  if (k >= 1 && c->upd_prev > 0.0) {
-    const double rho = upd / c->upd_prev;
+  if (k >= 1 && c0.upd_prev > 0.0) {
+    const double rho = upd / c0.upd_prev;
     if (rho < 1.0) est = rho / (1.0 - rho) * rel;
   }
   if (upd == 0.0) est = 0.0;
   c->est = est;
+  const double upd_first = k == 0 ? upd : c0.upd_first;
   if (k == 0) c->upd_first = upd;
   c->upd_prev = upd;
-  if (bad || (k >= 2 && upd > 1e3 * c->upd_first)) {
+  if (bad || (k >= 2 && upd > 1e3 * upd_first)) {
     c->status = PINT_EDIVERGED;
     c->done = 1;
   } else if (est <= f.safety * f.rtol || rel <= 1e-3 * f.rtol) {
@@ -655,11 +696,15 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
 
 // Stand-alone control kernel (one workgroup), used when the update kernel
 // does not run it itself.
-__global__ __launch_bounds__(256) void k_finalize(FinArgs f) {
+// One workgroup: 256 threads when the partials are few (its fixed cost is
+// lower), 1024 when there are many to stream (N_t x blocks per level large).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(FinArgs f) {
   if (f.ctrl->done) return;
-  __shared__ double red[4 * 256];
-  finalize_body<256>(f, red);
+  __shared__ double red[4 * (NT / 64)];
+  finalize_body<NT>(f, red);
 }
+constexpr int FIN_WIDE_SLOTS = 16384;
 
 // Control record reset and the first iteration's c_bar = mean(3 u^2) of the
 // initial guess (CH operators only): k_init_part writes workgroup partial
@@ -1020,7 +1065,11 @@ hipError_t launch_time(int nt, T* S, const TimeArgs<T>& ta, hipStream_t st) {
 }
 
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, f);
+  const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
+  if (size_t(f.nt) * gmax > size_t(FIN_WIDE_SLOTS))
+    hipLaunchKernelGGL(k_finalize<1024>, dim3(1), dim3(1024), 0, st, f);
+  else
+    hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, st, f);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
