@@ -39,6 +39,7 @@ PREC_DESC = {
     "bf16": "FP64 residual and forward DCT, BF16-operand MFMA time contraction (FP32 accumulate), FP32 inverse "
             "DCT, FP64 update",
     "bf16x3": "as bf16 with a two-term BF16 split of both operands (three products)",
+    "fp32_norefine": "FP32 residual, transforms and iterate, no refinement (stops on its plateau)",
 }
 
 WORKLOADS = {
@@ -387,6 +388,7 @@ def main():
         # variants get a second loop with events for the contraction kernel)
         out["paths"] = {}
         variants = [(o, "fft", None) for o in ("mixed", "fp32", "fp64") if o != args.precision]
+        variants += [("fp32_norefine", "fft", None)]  # the unrefined plateau (not at the 1e-10 bar)
         # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
         bf16_alpha = 4e-3 if name == "c5" else BF16_ALPHA
         variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", bf16_alpha),

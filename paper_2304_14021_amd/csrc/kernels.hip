@@ -72,21 +72,22 @@ struct rows_geom {
   static constexpr int ES = P + 1;                   // odd stride of the complex scratch
 };
 
-template <typename T, typename TO, int DIM, int N, int RB, int NT, int MODE>
+// RT: the residual's arithmetic type (double; float for the unrefined mode).
+template <typename T, typename TO, int DIM, int N, int RB, int NT, int MODE, typename RT>
 __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S, double* __restrict__ rout,
                                                   DctTables<T> dt) {
   if (a.done && *a.done) return;
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
-  constexpr int VB = VR * N * 8, GB = GR * N * 8, ZB = N * ES * int(sizeof(cx<T>));
+  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
   constexpr int R0 = VB > ZB ? VB : ZB;
   constexpr int NV = DIM == 2 ? 1 : RB;
   constexpr int RED = NT * NV * 8;  // reduction scratch, reuses the G region
   __shared__ __align__(16) unsigned char lds[R0 + (GB > RED ? GB : RED)];
   __shared__ cx<T> s_tw[N], s_wq[N];
-  double* V = reinterpret_cast<double*>(lds);
+  RT* V = reinterpret_cast<RT*>(lds);
   cx<T>* z = reinterpret_cast<cx<T>*>(lds);
-  double* G = reinterpret_cast<double*>(lds + R0);
+  RT* G = reinterpret_cast<RT*>(lds + R0);
   if (MODE == 0) {
     table_to_lds<T, NT, N>(s_tw, dt.tw);
     table_to_lds<T, NT, N>(s_wq, dt.wq);
@@ -98,13 +99,14 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
   const bool bc = a.bcast != 0;
   const double th = a.theta, omth = 1.0 - a.theta;
+  const RT thr = RT(th), omr = RT(omth);
 
   // Phase 1: v at positions y0-2 .. y0+RB+1 (clamped rows) -> V.  The own
   // rows' time differences d = u_n - u_{n-1} stay in registers for phase 3
   // (same point-to-thread map).  All loads are issued before any is used.
   constexpr int HW = 2 * Gm::H * N, OW = RB * N;
   constexpr int ITH = cdiv_i(HW, NT), ITO = cdiv_i(OW, NT);
-  double d[ITO];
+  RT d[ITO];
   {
     double hn[ITH > 0 ? ITH : 1], hm[ITH > 0 ? ITH : 1], on[ITO], om[ITO];
 #pragma unroll
@@ -146,14 +148,14 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
       if (HW % NT == 0 || w < HW) {
         const int hr = w / N, x = w - (w / N) * N;
         const int vr = hr < Gm::H ? hr : hr + RB;
-        V[vr * N + x] = th * hn[i] + omth * hm[i];
+        V[vr * N + x] = thr * RT(hn[i]) + omr * RT(hm[i]);
       }
     }
 #pragma unroll
     for (int i = 0; i < ITO; ++i) {
       const int w = tid + i * NT;
-      d[i] = on[i] - om[i];
-      if (OW % NT == 0 || w < OW) V[Gm::H * N + w] = th * on[i] + omth * om[i];
+      d[i] = RT(on[i]) - RT(om[i]);
+      if (OW % NT == 0 || w < OW) V[Gm::H * N + w] = thr * RT(on[i]) + omr * RT(om[i]);
     }
   }
   __syncthreads();
@@ -167,15 +169,15 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     } else {
       c = gr;
     }
-    const double v = V[c * N + x];
-    double lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - 2.0 * v;
-    if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - 2.0 * v;
-    double g = a.c3 * v * v * v + a.c1 * v + a.c2 * (lap * a.inv_h2);
+    const RT v = V[c * N + x];
+    RT lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - RT(2) * v;
+    if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - RT(2) * v;
+    RT g = RT(a.c3) * v * v * v + RT(a.c1) * v + RT(a.c2) * (lap * RT(a.inv_h2));
     if (a.c1p != 0.0) {
       const int n = DIM == 2 ? lev : lev + gr;
       const int off = DIM == 2 ? yg * N + x : x;
-      const double um = (bc || n == 0) ? a.u0[off] : a.U[(n - 1) * ns + off];
-      g += a.c1p * um;
+      const RT um = RT((bc || n == 0) ? a.u0[off] : a.U[(n - 1) * ns + off]);
+      g += RT(a.c1p) * um;
     }
     G[idx] = g;
   }
@@ -190,17 +192,17 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     if (!(OW % NT == 0 || w < OW)) continue;
     const int rr = w / N, x = w - (w / N) * N;
     const int gc = DIM == 2 ? rr + 1 : rr;
-    const double gv = G[gc * N + x];
-    double lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - 2.0 * gv;
-    if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - 2.0 * gv;
-    const double r = -d[i] * a.inv_dt + lap * a.inv_h2;
+    const RT gv = G[gc * N + x];
+    RT lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - RT(2) * gv;
+    if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - RT(2) * gv;
+    const RT r = -d[i] * RT(a.inv_dt) + lap * RT(a.inv_h2);
 #pragma unroll
     for (int qq = 0; qq < NV; ++qq)
-      if (DIM == 2 || qq == rr) rsq[qq] += r * r;
+      if (DIM == 2 || qq == rr) rsq[qq] += double(r) * double(r);
     if (MODE == 1) {
       const int n = DIM == 2 ? lev : lev + rr;
       const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-      rout[n * ns + off] = r;
+      rout[n * ns + off] = double(r);
     } else {
       comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(r);
     }
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   bool ismax[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) ismax[q] = false;
-  block_reduce<NT, NV>(G, rsq, ismax);
+  block_reduce<NT, NV>(reinterpret_cast<double*>(G), rsq, ismax);
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -329,7 +331,8 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
           dout[gi] = del;
           continue;
         }
-        const double u = uo[q] + del;
+        // unrefined mode: the iterate is an FP32 quantity, updated in FP32
+        const double u = a.round32 ? double(float(uo[q]) + float(del)) : uo[q] + del;
         a.U[gi] = u;
 #pragma unroll
         for (int qq = 0; qq < NV; ++qq) {
@@ -674,6 +677,11 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
   } else if (est <= f.safety * f.rtol || rel <= 1e-3 * f.rtol) {
     c->status = PINT_OK;
     c->done = 1;
+  } else if (f.stagnate && k >= 2 && c0.upd_prev > 0.0 && upd > 0.5 * c0.upd_prev) {
+    // unrefined mode: the update stopped contracting, the iterate sits on
+    // its working-precision plateau
+    c->status = PINT_OK;
+    c->done = 1;
   } else if (k + 1 >= f.max_iter) {
     c->status = PINT_ENOCONV;
     c->done = 1;
@@ -870,26 +878,27 @@ int rows_levels_per_block(int dim, int n) {
   return dim == 1 ? row_cfg<1, 8>::RB : 1;
 }
 
-template <typename T, typename TO, int DIM, int N, bool WIDE>
+template <typename T, typename TO, int DIM, int N, bool WIDE, typename RT>
 static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
   using C = row_fwd_cfg<DIM, N, WIDE>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
-    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, rout,
-                       dt);
+    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
+                       rout, dt);
   else
-    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, rout,
-                       dt);
+    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 1, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
+                       rout, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-template <typename T, typename TO, int DIM, int N>
+template <typename T, typename TO, int DIM, int N, typename RT>
 static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
-  if (DIM == 2 && N >= 256 && rows_fwd_wide()) return launch_rows_fwd_w<T, TO, DIM, N, true>(a, S, rout, dt, nt, mode, st);
-  return launch_rows_fwd_w<T, TO, DIM, N, false>(a, S, rout, dt, nt, mode, st);
+  if (DIM == 2 && N >= 256 && rows_fwd_wide())
+    return launch_rows_fwd_w<T, TO, DIM, N, true, RT>(a, S, rout, dt, nt, mode, st);
+  return launch_rows_fwd_w<T, TO, DIM, N, false, RT>(a, S, rout, dt, nt, mode, st);
 }
 
 template <typename T, int DIM, int N>
@@ -944,11 +953,11 @@ static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const D
     default: return hipErrorInvalidValue; \
   }
 
-template <typename T, typename TO>
+template <typename T, typename TO, typename RT>
 hipError_t launch_rows_fwd(int dim, int n, const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                            int mode, hipStream_t st) {
-#define C1_(NN) launch_rows_fwd_n<T, TO, 1, NN>(a, S, rout, dt, nt, mode, st)
-#define C2_(NN) launch_rows_fwd_n<T, TO, 2, NN>(a, S, rout, dt, nt, mode, st)
+#define C1_(NN) launch_rows_fwd_n<T, TO, 1, NN, RT>(a, S, rout, dt, nt, mode, st)
+#define C2_(NN) launch_rows_fwd_n<T, TO, 2, NN, RT>(a, S, rout, dt, nt, mode, st)
   if (dim == 2) {
     PINT_SWITCH_N(C2_)
   }
@@ -1100,11 +1109,13 @@ hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st) {
   return hipSuccess;
 }
 
-template hipError_t launch_rows_fwd<float, float>(int, int, const ResidArgs&, float*, double*,
-                                                  const DctTables<float>&, int, int, hipStream_t);
-template hipError_t launch_rows_fwd<double, double>(int, int, const ResidArgs&, double*, double*,
-                                                    const DctTables<double>&, int, int, hipStream_t);
-template hipError_t launch_rows_fwd<double, float>(int, int, const ResidArgs&, float*, double*,
+template hipError_t launch_rows_fwd<float, float, double>(int, int, const ResidArgs&, float*, double*,
+                                                          const DctTables<float>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<float, float, float>(int, int, const ResidArgs&, float*, double*,
+                                                         const DctTables<float>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<double, double, double>(int, int, const ResidArgs&, double*, double*,
+                                                            const DctTables<double>&, int, int, hipStream_t);
+template hipError_t launch_rows_fwd<double, float, double>(int, int, const ResidArgs&, float*, double*,
                                                    const DctTables<double>&, int, int, hipStream_t);
 template hipError_t launch_rows_inv<float>(int, int, const UpdArgs&, const float*, double*, const DctTables<float>&,
                                            int, int, hipStream_t);

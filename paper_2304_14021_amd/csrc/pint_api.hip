@@ -49,6 +49,7 @@ struct pint_plan {
   bool fp64;   // working precision W = double
   bool mixed;  // FP64 forward spatial transform, FP32 time solve and inverse
   int dense = -1;  // DenseKind of the time contraction on the matrix cores, -1: FFT path
+  bool norefine = false;  // residual and iterate in FP32 (no refinement)
   std::string err;
 
   // device tables (one allocation), FP64 then FP32 copies
@@ -145,8 +146,10 @@ int validate(const pint_problem* p, std::string* err) {
   if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
   if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
   if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED &&
-      p->precision != PINT_PREC_BF16_REFINE)
+      p->precision != PINT_PREC_BF16_REFINE && p->precision != PINT_PREC_FP32_NOREFINE)
     return set_err(err, PINT_EINVAL, "precision not supported by this build");
+  if (p->precision == PINT_PREC_FP32_NOREFINE && p->time_path == PINT_TIME_DENSE)
+    return set_err(err, PINT_EINVAL, "the unrefined mode uses the FFT time path");
   if (p->time_path != PINT_TIME_AUTO && p->time_path != PINT_TIME_FFT && p->time_path != PINT_TIME_DENSE)
     return set_err(err, PINT_EINVAL, "unknown time path");
   if (p->precision == PINT_PREC_FP64 && p->time_path == PINT_TIME_DENSE)
@@ -455,7 +458,7 @@ hipError_t launch_time_any(const pint_plan* pl, T* S, const TimeArgs<T>& ta, hip
   return launch_time<T>(pl->nt, S, ta, st);
 }
 
-template <typename TF, typename T>
+template <typename TF, typename T, typename RT = double>
 int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, hipStream_t st,
                       hipEvent_t* evs, bool bcast, Ctrl* host) {
   TimeArgs<T> ta = time_args<T>(pl);
@@ -467,18 +470,19 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.part = w.part;
   ra.done = &w.ctrl->done;
   ra.bcast = bcast ? 1 : 0;
-  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->dof, pl->rtol, pl->safety};
-  UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0};
+  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->norefine ? 1 : 0,
+             pl->dof, pl->rtol, pl->safety};
+  UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0, pl->norefine ? 1 : 0};
   T* S = static_cast<T*>(w.S);
   TF* SF = std::is_same<TF, T>::value ? reinterpret_cast<TF*>(w.S) : static_cast<TF*>(w.S64);
   const int* done = &w.ctrl->done;
   auto ev = [&](int i) -> hipError_t { return evs ? hipEventRecord(evs[i], st) : hipSuccess; };
   HIPCHK(ev(0), "hipEventRecord");
   if (pl->dim == 2)
-    HIPCHK((launch_rows_fwd<TF, TF>(2, pl->n, ra, SF, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
+    HIPCHK((launch_rows_fwd<TF, TF, RT>(2, pl->n, ra, SF, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
            "residual + x-DCT kernel");
   else
-    HIPCHK((launch_rows_fwd<TF, T>(1, pl->n, ra, S, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
+    HIPCHK((launch_rows_fwd<TF, T, RT>(1, pl->n, ra, S, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
            "residual + x-DCT kernel");
   HIPCHK(ev(1), "hipEventRecord");
   if (pl->dim == 2)
@@ -501,6 +505,7 @@ int enqueue_any(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, h
                 bool bcast, Ctrl* host) {
   if (pl->fp64) return enqueue_iteration<double, double>(pl, d_u0, d_U, w, st, evs, bcast, host);
   if (pl->mixed) return enqueue_iteration<double, float>(pl, d_u0, d_U, w, st, evs, bcast, host);
+  if (pl->norefine) return enqueue_iteration<float, float, float>(pl, d_u0, d_U, w, st, evs, bcast, host);
   return enqueue_iteration<float, float>(pl, d_u0, d_U, w, st, evs, bcast, host);
 }
 
@@ -576,6 +581,7 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   // BF16 keeps the FP64 forward spatial transform of the mixed mode
   pl->mixed = p->precision == PINT_PREC_MIXED || p->precision == PINT_PREC_BF16_REFINE;
   pl->dense = dense_kind_of(p);
+  pl->norefine = p->precision == PINT_PREC_FP32_NOREFINE;
   pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
   pl->nbl_f = rows_fwd_blocks_per_level(pl->dim, pl->n);
   if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {

@@ -51,7 +51,8 @@ struct FinArgs {
   Ctrl* host;  // pinned host mirror of the status fields (nullable)
   const double* part;
   int nt, nbl, max_iter;
-  int nbl_f;  // blocks per level of the forward row pass (its residual partials)
+  int nbl_f;     // blocks per level of the forward row pass (its residual partials)
+  int stagnate;  // unrefined mode: also stop once the update stops contracting
   double dof, rtol, safety;
 };
 
@@ -61,6 +62,7 @@ struct UpdArgs {
   double* part;
   const int* done;
   int bcast;        // U_n = u0 + delta_n instead of U_n += delta_n
+  int round32;      // store U_n rounded to FP32 (unrefined mode)
 };
 
 template <typename T>
@@ -110,8 +112,9 @@ int rows_blocks_per_level(int dim, int n);
 int rows_fwd_blocks_per_level(int dim, int n);
 int rows_levels_per_block(int dim, int n);
 
-// Forward row pass computing in T, storing the x-DCT in TO.
-template <typename T, typename TO>
+// Forward row pass: residual in RT arithmetic (double; float for the
+// unrefined mode), x-DCT computed in T, stored in TO.
+template <typename T, typename TO, typename RT = double>
 hipError_t launch_rows_fwd(int dim, int n, const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                            int mode, hipStream_t st);
 template <typename T>
