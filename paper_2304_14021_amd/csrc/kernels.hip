@@ -827,7 +827,7 @@ template <int DIM, int N, bool WIDE>
 struct row_fwd_cfg {
   static constexpr int RB = (DIM == 2 && N >= 256 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
   // 2D N <= 128: 512 threads per block shorten each thread's serial chain
-  static constexpr int NT0 = (DIM == 2 && N <= 128 && N >= 64) ? 512 : 256;
+  static constexpr int NT0 = (DIM == 2 && N >= 64) ? 512 : 256;
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
