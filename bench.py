@@ -30,7 +30,7 @@ BF16_ALPHA = 1e-2  # alpha of the BF16 runs (coarser contraction, larger alpha)
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives),
 # profiles/c2_mixed_hbm_traffic.md.  Valid for the kernel as measured: drop the
 # entry when that kernel changes.
-MEASURED_TRAFFIC = {("c2", "mixed", "rows_fwd"): (11578.8 * 2.0 + 16400.0) * 1024}
+MEASURED_TRAFFIC = {("c2", "mixed", "rows_fwd"): (11562.3 * 2.0 + 16400.0) * 1024}
 PREC_DESC = {
     "mixed": "FP64 residual, FP64 forward DCT, FP32 time FFT solve and inverse DCT, FP64 update "
              "(iterative refinement)",

@@ -588,16 +588,17 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
 // stop when est <= safety * rtol (k >= 2, rho < 1) or rel <= 1e-3 rtol;
 // diverged on NaN/Inf or when the update grows 1e3-fold over the first one.
 // The scalar averaged Jacobian for the next time solve is mean(3 u^2).
-// Per-level sums: a group of g lanes (g = the power of two >= the blocks per
-// level, at most 64) reads one level's block partials together, several
-// levels per wave and FL levels per lane in flight, and combines them with a
-// fixed xor-shuffle tree, so every sum is formed in the same order each run.
 // Control-record fields the stop rule reads, loaded by thread 0 before the
 // reduction so that their latency overlaps it.
 struct CtrlPrev {
   int iter;
   double upd_prev, upd_first;
 };
+
+template <int NT>
+__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]);
+template <int NT>
+__device__ void finalize_control(const FinArgs& f, double* red, double (&v)[4], const CtrlPrev& c0);
 
 template <int NT>
 __device__ void finalize_body(const FinArgs& f, double* red) {
@@ -607,14 +608,42 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
     c0.upd_prev = f.ctrl->upd_prev;
     c0.upd_first = f.ctrl->upd_first;
   }
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // max dsq, max usq, sum u2, max rsq
+  if constexpr (NT <= 256) {
+    // few partials: one thread per level, its block partials in order
+    for (int n = threadIdx.x; n < f.nt; n += NT) {
+      double dsq = 0.0, usq = 0.0, u2 = 0.0, rsq = 0.0;
+      for (int bb = 0; bb < f.nbl; ++bb) {
+        const double* pp = f.part + (size_t(n) * f.nbl + bb) * PART_STRIDE;
+        dsq += pp[PART_DSQ];
+        usq += pp[PART_USQ];
+        u2 += pp[PART_U2];
+      }
+      for (int bb = 0; bb < f.nbl_f; ++bb) rsq += f.part[(size_t(n) * f.nbl_f + bb) * PART_STRIDE + PART_RSQ];
+      v[0] = (dsq != dsq || dsq > v[0]) ? dsq : v[0];
+      v[1] = (usq != usq || usq > v[1]) ? usq : v[1];
+      v[2] += u2;
+      v[3] = (rsq != rsq || rsq > v[3]) ? rsq : v[3];
+    }
+  } else {
+    finalize_levels_grouped<NT>(f, v);
+  }
+  finalize_control<NT>(f, red, v, c0);
+}
+
+// Many partials: a group of g lanes (g = the power of two >= the blocks per
+// level, at most 64) reads one level's block partials together, several
+// levels per wave and FL levels per lane in flight, and combines them with a
+// fixed xor-shuffle tree, so every sum is formed in the same order each run.
+template <int NT>
+__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]) {
   constexpr int NW = NT / 64, FL = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
   int g = 1;
   while (g < gmax && g < 64) g <<= 1;
   const int lpw = 64 / g;  // levels per wave per step
-  const int sub = lane / g, j = lane - (lane / g) * g;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};  // max dsq, max usq, sum u2, max rsq (group leaders)
+  const int sub = lane / g, j = lane - (lane / g) * g;  // v: group leaders accumulate
   for (int base = wave * lpw; base < f.nt; base += NW * lpw * FL) {
     double s[FL][4];
 #pragma unroll
@@ -646,6 +675,11 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
       }
     }
   }
+}
+
+// Reduction over threads and the stop rule (thread 0).
+template <int NT>
+__device__ void finalize_control(const FinArgs& f, double* red, double (&v)[4], const CtrlPrev& c0) {
   const bool ismax[4] = {true, true, false, true};
   block_reduce_waves<NT, 4>(red, v, ismax);
   if (threadIdx.x != 0) return;
