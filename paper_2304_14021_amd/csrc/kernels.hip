@@ -30,6 +30,8 @@
 
 namespace pint {
 
+thread_local hipEvent_t g_launch_ev0 = nullptr, g_launch_ev1 = nullptr;
+
 // Neumann (ghost-reflection) index clamp.
 __device__ __forceinline__ int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
@@ -920,10 +922,10 @@ static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, con
   using C = row_fwd_cfg<DIM, N, WIDE>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
-    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
+    PINT_LAUNCH((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
                        rout, dt);
   else
-    hipLaunchKernelGGL((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 1, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
+    PINT_LAUNCH((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 1, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
                        rout, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
@@ -943,9 +945,9 @@ static hipError_t launch_rows_inv_n(const UpdArgs& a, const T* S, double* dout, 
   using C = row_cfg<DIM, N>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
-    hipLaunchKernelGGL((k_rows_inv<T, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
+    PINT_LAUNCH((k_rows_inv<T, DIM, N, C::RB, C::NT, 0>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
   else
-    hipLaunchKernelGGL((k_rows_inv<T, DIM, N, C::RB, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
+    PINT_LAUNCH((k_rows_inv<T, DIM, N, C::RB, C::NT, 1>), dim3(grid), dim3(C::NT), 0, st, a, S, dout, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -955,9 +957,9 @@ static hipError_t launch_rows_dct_n(const T* in, T* out, const DctTables<T>& dt,
   using C = row_cfg<DIM, N>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (!inv)
-    hipLaunchKernelGGL((k_rows_dct<T, DIM, N, C::RB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
+    PINT_LAUNCH((k_rows_dct<T, DIM, N, C::RB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
   else
-    hipLaunchKernelGGL((k_rows_dct<T, DIM, N, C::RB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
+    PINT_LAUNCH((k_rows_dct<T, DIM, N, C::RB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, in, out, dt);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -968,9 +970,9 @@ static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const D
   using C = col_cfg<N>;
   const int grid = nt * (N / C::XB);
   if (!inv)
-    hipLaunchKernelGGL((k_cols<T, TO, N, C::XB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
+    PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
   else if constexpr (std::is_same<T, TO>::value)
-    hipLaunchKernelGGL((k_cols<T, TO, N, C::XB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
+    PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
   else
     return hipErrorInvalidValue;
   PINT_CHECK_LAUNCH();
@@ -1072,7 +1074,7 @@ static hipError_t launch_time_m(T* S, const TimeArgs<T>& ta, hipStream_t st) {
   if constexpr (M > time_cfg<T, NTT>::MMAX || M < 2) {
     return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((k_time_solve<T, NTT, M, 256>), dim3(ta.ns / M), dim3(256), 0, st, S, ta);
+    PINT_LAUNCH((k_time_solve<T, NTT, M, 256>), dim3(ta.ns / M), dim3(256), 0, st, S, ta);
     PINT_CHECK_LAUNCH();
     return hipSuccess;
   }
@@ -1112,9 +1114,9 @@ hipError_t launch_time(int nt, T* S, const TimeArgs<T>& ta, hipStream_t st) {
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st) {
   const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
   if (size_t(f.nt) * gmax > size_t(FIN_WIDE_SLOTS))
-    hipLaunchKernelGGL(k_finalize<1024>, dim3(1), dim3(1024), 0, st, f);
+    PINT_LAUNCH(k_finalize<1024>, dim3(1), dim3(1024), 0, st, f);
   else
-    hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, st, f);
+    PINT_LAUNCH(k_finalize<256>, dim3(1), dim3(256), 0, st, f);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1124,23 +1126,23 @@ hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool 
   if (need_cbar) {
     const size_t total = a.broadcast ? size_t(a.ns) : size_t(a.ns) * a.nt;
     nparts = int((total + INIT_CHUNK - 1) / INIT_CHUNK);
-    hipLaunchKernelGGL(k_init_part, dim3(nparts), dim3(256), 0, st, a);
+    PINT_LAUNCH(k_init_part, dim3(nparts), dim3(256), 0, st, a);
     PINT_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(256), 0, st, c, host, a, dof, nparts);
+  PINT_LAUNCH(k_init_ctrl, dim3(1), dim3(256), 0, st, c, host, a, dof, nparts);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
 template <typename TI, typename TO>
 hipError_t launch_cast(const TI* in, TO* out, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((k_cast<TI, TO>), dim3(1024), dim3(256), 0, st, in, out, n);
+  PINT_LAUNCH((k_cast<TI, TO>), dim3(1024), dim3(256), 0, st, in, out, n);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }
 
 hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st) {
-  hipLaunchKernelGGL(k_diagnostics, dim3(nt), dim3(256), 0, st, a);
+  PINT_LAUNCH(k_diagnostics, dim3(nt), dim3(256), 0, st, a);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -428,7 +428,7 @@ int hip_fail(pint_plan* pl, hipError_t e, const char* what) {
     if (e__ != hipSuccess) return hip_fail(pl, e__, what); \
   } while (0)
 
-constexpr int EV_PER_IT = 7;  // events bracketing the 6 kernels of one iteration
+constexpr int EV_PER_IT = 12;  // a (start, stop) event pair for each of the 6 kernels of one iteration
 
 template <typename T>
 const DctTables<T>& dct_tables(const pint_plan* pl);
@@ -476,28 +476,33 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   T* S = static_cast<T*>(w.S);
   TF* SF = std::is_same<TF, T>::value ? reinterpret_cast<TF*>(w.S) : static_cast<TF*>(w.S64);
   const int* done = &w.ctrl->done;
-  auto ev = [&](int i) -> hipError_t { return evs ? hipEventRecord(evs[i], st) : hipSuccess; };
-  HIPCHK(ev(0), "hipEventRecord");
+  // stage timing: each kernel is bracketed by its own (start, stop) event pair
+  auto ev = [&](int stage) {
+    if (evs) set_launch_events(evs[2 * stage], evs[2 * stage + 1]);
+  };
+  ev(0);
   if (pl->dim == 2)
     HIPCHK((launch_rows_fwd<TF, TF, RT>(2, pl->n, ra, SF, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
            "residual + x-DCT kernel");
   else
     HIPCHK((launch_rows_fwd<TF, T, RT>(1, pl->n, ra, S, nullptr, dct_tables<TF>(pl), pl->nt, 0, st)),
            "residual + x-DCT kernel");
-  HIPCHK(ev(1), "hipEventRecord");
-  if (pl->dim == 2)
+  if (pl->dim == 2) {
+    ev(1);
     HIPCHK((launch_cols<TF, T>(pl->n, SF, S, done, dct_tables<TF>(pl), pl->nt, false, st)), "y-DCT kernel");
-  HIPCHK(ev(2), "hipEventRecord");
+  }
+  ev(2);
   HIPCHK(launch_time_any<T>(pl, S, ta, st), "time-solve kernel");
-  HIPCHK(ev(3), "hipEventRecord");
-  if (pl->dim == 2)
+  if (pl->dim == 2) {
+    ev(3);
     HIPCHK((launch_cols<T, T>(pl->n, S, S, done, dct_tables<T>(pl), pl->nt, true, st)), "y-DCT-III kernel");
-  HIPCHK(ev(4), "hipEventRecord");
+  }
+  ev(4);
   HIPCHK(launch_rows_inv<T>(pl->dim, pl->n, ua, S, nullptr, dct_tables<T>(pl), pl->nt, 0, st),
          "x-DCT-III + update kernel");
-  HIPCHK(ev(5), "hipEventRecord");
+  ev(5);
   HIPCHK(launch_finalize(fa, st), "control kernel");
-  HIPCHK(ev(6), "hipEventRecord");
+  set_launch_events(nullptr, nullptr);
   return PINT_OK;
 }
 
@@ -822,9 +827,10 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
     fill_report(pl, c, status, rep);
     if (timing) {
       for (int k = 0; k < c.iter && k < it; ++k)
-        for (int s = 0; s < EV_PER_IT - 1; ++s) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, pl->ev[EV_PER_IT * k + s], pl->ev[EV_PER_IT * k + s + 1]) == hipSuccess)
+        for (int s = 0; s < EV_PER_IT / 2; ++s) {
+          float ms = 0.f;  // stages without a kernel (the column passes in 1D) stay 0
+          if (hipEventElapsedTime(&ms, pl->ev[EV_PER_IT * k + 2 * s], pl->ev[EV_PER_IT * k + 2 * s + 1]) ==
+              hipSuccess)
             rep->ms_stage[s] += ms;
         }
     }

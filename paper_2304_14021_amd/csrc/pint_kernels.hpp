@@ -3,11 +3,31 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 
 #include "device_common.hpp"
 
 namespace pint {
+
+// Stage timing: when set, the next kernel launch of this thread is bracketed by
+// these events, stamped by the dispatch itself (hipExtLaunchKernelGGL), so the
+// elapsed time is the kernel's own duration.  A launch consumes them.
+extern thread_local hipEvent_t g_launch_ev0, g_launch_ev1;
+inline void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_launch_ev0 = start;
+  g_launch_ev1 = stop;
+}
+#define PINT_LAUNCH(K, G, B, S, ST, ...)                                                              \
+  do {                                                                                                \
+    if (::pint::g_launch_ev0) {                                                                       \
+      hipEvent_t e0_ = ::pint::g_launch_ev0, e1_ = ::pint::g_launch_ev1;                               \
+      ::pint::g_launch_ev0 = ::pint::g_launch_ev1 = nullptr;                                          \
+      hipExtLaunchKernelGGL(K, G, B, S, ST, e0_, e1_, 0, __VA_ARGS__);                                \
+    } else {                                                                                          \
+      hipLaunchKernelGGL(K, G, B, S, ST, __VA_ARGS__);                                                \
+    }                                                                                                 \
+  } while (0)
 
 constexpr int PINT_HIST_DEV = 64;
 // status codes mirrored from the public header (kept in sync by a static_assert

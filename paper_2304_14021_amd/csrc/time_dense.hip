@@ -237,7 +237,7 @@ template <int KIND, int NTT>
 hipError_t launch_dense_nt(float* S, const TimeArgs<float>& ta, const DenseArgs& da, hipStream_t st) {
   constexpr int NB = dense_nb(NTT);
   if (ta.ns % NB != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_time_dense<KIND, NTT>), dim3(ta.ns / NB), dim3(256), 0, st, S, ta, da);
+  PINT_LAUNCH((k_time_dense<KIND, NTT>), dim3(ta.ns / NB), dim3(256), 0, st, S, ta, da);
   return hipGetLastError();
 }
 
