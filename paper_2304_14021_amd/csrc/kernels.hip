@@ -511,7 +511,14 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
   __shared__ cx<T> s_tw[NTT];
   table_to_lds<T, NT, NTT>(s_tw, ta.tw);
   const int tid = threadIdx.x;
-  const int col0 = blockIdx.x * M;
+  // Tiles narrower than a 128-byte line share lines with their neighbours.
+  // Workgroups are dealt to the 8 XCDs round-robin; this order gives XCD x
+  // the contiguous range of tiles [x B/8, (x+1) B/8) (B tiles), so the tiles
+  // sharing a line read it through one L2.
+  const int nb = gridDim.x;
+  const int tile = (M * int(sizeof(T)) < 128 && (nb & 7) == 0) ? int(blockIdx.x & 7) * (nb >> 3) + int(blockIdx.x >> 3)
+                                                                 : int(blockIdx.x);
+  const int col0 = tile * M;
   const size_t ns = ta.ns;
   constexpr int W = NTT * C, IT = cdiv_i(W, NT);
   {
