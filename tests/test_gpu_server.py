@@ -220,3 +220,22 @@ def test_host_results_wait_in_pinned_pool_until_collected():
         U, rep = srv.wait(t)
         assert srv.stats()["host_pool_in_use"] == 0
     assert np.array_equal(U, _solo(p, u0, "fp64")[0])
+
+
+def test_served_dense_bf16_requests():
+    # requests on the dense matrix-core time path (BF16 split), replayed from
+    # captured graphs, equal their standalone solves bit for bit
+    base = Problem(op="linear_ch", dim=2, n=64, nt=64, dt=1e-5, eps=0.05, beta=0.3, alpha=1e-2)
+    ps = [dataclasses.replace(base, eps=e) for e in (0.04, 0.06)]
+    rng = np.random.default_rng(17)
+    u0s = [rng.uniform(-0.05, 0.05, base.slice_shape) for _ in ps]
+    with Server(1 << 28, max_active=2, device=dev()) as srv:
+        ts = [srv.submit(p, u, precision="bf16x3") for p, u in zip(ps, u0s)]
+        res = [srv.wait(t) for t in ts]
+        st = srv.stats()
+    assert st["completed"] == 2 and st["graph_launches"] >= 1
+    for p, u0, (U, rep) in zip(ps, u0s, res):
+        ref, rrep = _solo(p, u0, "bf16x3")
+        assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
+        assert np.array_equal(U, ref)
+        assert stepper.rel_err(U, stepper.sequential(p, u0)) <= 1e-10
