@@ -528,7 +528,30 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
   const int col0 = tile * M;
   const size_t ns = ta.ns;
   constexpr int W = NTT * C, IT = cdiv_i(W, NT);
-  {
+  // FP32: two complex values (16 bytes) per load and store
+  constexpr bool V2 = std::is_same<T, float>::value && C % 2 == 0;
+  constexpr int W2 = W / 2, IT2 = cdiv_i(W2, NT), C2 = C / 2;
+  if constexpr (V2) {
+    float4 x[IT2];
+#pragma unroll
+    for (int i = 0; i < IT2; ++i) {
+      const int w = tid + i * NT;
+      if (W2 % NT == 0 || w < W2) {
+        const int j = w / C2, c = w - (w / C2) * C2;
+        x[i] = *reinterpret_cast<const float4*>(S + j * ns + col0 + 4 * c);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IT2; ++i) {
+      const int w = tid + i * NT;
+      if (W2 % NT == 0 || w < W2) {
+        const int j = w / C2;
+        const T s = ta.aj[j];
+        z[2 * w] = scale(mk(T(x[i].x), T(x[i].y)), s);
+        z[2 * w + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
+      }
+    }
+  } else {
     // issue every load of the tile before using any (latency hiding)
     cx<T> x[IT];
 #pragma unroll
@@ -587,12 +610,25 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
   }
   __syncthreads();
   fft_lds<T, NTT, C, C, NT, +1>(z, s_tw);
+  if constexpr (V2) {
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int w = tid + i * NT;
-    if (W % NT == 0 || w < W) {
-      const int j = w / C, c = w - (w / C) * C;
-      *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+    for (int i = 0; i < IT2; ++i) {
+      const int w = tid + i * NT;
+      if (W2 % NT == 0 || w < W2) {
+        const int j = w / C2, c = w - (w / C2) * C2;
+        const T s = ta.aij[j];
+        const cx<T> a = scale(z[2 * w], s), b = scale(z[2 * w + 1], s);
+        *reinterpret_cast<float4*>(S + j * ns + col0 + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int w = tid + i * NT;
+      if (W % NT == 0 || w < W) {
+        const int j = w / C, c = w - (w / C) * C;
+        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+      }
     }
   }
 }
