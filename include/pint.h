@@ -94,6 +94,12 @@ extern "C" {
 /* ----------------------------------------------------------------- flags */
 #define PINT_FLAG_INIT_BROADCAST_U0 0x1u /* fill d_U with u0 before iterating */
 #define PINT_FLAG_STAGE_TIMING      0x2u /* fill pint_report.ms_stage (adds syncs) */
+#define PINT_FLAG_SOLVE_GRAPH       0x8u /* pint_solve on a non-NULL stream: capture
+                                            the init and the predicted iterations
+                                            as one HIP graph, replayed by later
+                                            solves with the same buffers, stream
+                                            and iteration count (ignored with
+                                            PINT_FLAG_STAGE_TIMING)            */
 #define PINT_FLAG_BF16_SPLIT        0x4u /* PINT_PREC_BF16_REFINE: two-term BF16
                                             split of both operands, three
                                             products (hi*hi + hi*lo + lo*hi) */

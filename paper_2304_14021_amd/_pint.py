@@ -24,6 +24,7 @@ TIME_PATHS = {"auto": 0, "fft": 1, "dense": 2}
 FLAG_INIT_BROADCAST_U0 = 0x1
 FLAG_STAGE_TIMING = 0x2
 FLAG_BF16_SPLIT = 0x4
+FLAG_SOLVE_GRAPH = 0x8
 HIST = 64
 
 # Every symbol include/pint.h declares (checked by the CPU test suite).

@@ -69,7 +69,17 @@ struct pint_plan {
   Ctrl* h_ctrl = nullptr;  // pinned host mirror written by the control kernel
   std::vector<hipEvent_t> ev;
 
+  // solve graph (PINT_FLAG_SOLVE_GRAPH): init + the predicted iterations,
+  // valid for the buffers, stream and iteration count it was captured with
+  hipGraphExec_t gexec = nullptr;
+  const void* g_u0 = nullptr;
+  const void* g_U = nullptr;
+  const void* g_work = nullptr;
+  hipStream_t g_st = nullptr;
+  int g_iters = 0;
+
   ~pint_plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     if (d_tab && own_tab) (void)hipFree(d_tab);
     if (h_ctrl) (void)hipHostFree(h_ctrl);
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -800,13 +810,50 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
     }
   }
   const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
-  rc = begin_solve(pl, d_u0, d_U, w, st, pl->h_ctrl);
-  if (rc) return rc;
   // Enqueue as many iterations as the previous solve of this plan needed
   // (kernels after the device stop flag is set return at once), then check
   // the flag after each further iteration.
   int it = 0;
   const int first_check = std::min(std::max(pl->predict, 2), pl->max_iter);
+  const bool use_graph = (pl->p.flags & PINT_FLAG_SOLVE_GRAPH) && !timing && st != nullptr;
+  if (use_graph) {
+    // init + the predicted iterations as one graph, captured once per
+    // (buffers, stream, iteration count) and replayed afterwards
+    if (!(pl->gexec && pl->g_u0 == d_u0 && pl->g_U == d_U && pl->g_work == d_work && pl->g_st == st &&
+          pl->g_iters == first_check)) {
+      if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+      pl->gexec = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      int rc2 = begin_solve(pl, d_u0, d_U, w, st, pl->h_ctrl);
+      for (int k = 0; k < first_check && !rc2; ++k)
+        rc2 = enqueue_any(pl, d_u0, d_U, w, st, nullptr, bcast && k == 0, pl->h_ctrl);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &g);
+      if (rc2) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc2;
+      }
+      if (e != hipSuccess) return hip_fail(pl, e, "hipStreamEndCapture");
+      const hipError_t e2 = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) {
+        pl->gexec = nullptr;
+        return hip_fail(pl, e2, "hipGraphInstantiate");
+      }
+      pl->g_u0 = d_u0;
+      pl->g_U = d_U;
+      pl->g_work = d_work;
+      pl->g_st = st;
+      pl->g_iters = first_check;
+    }
+    HIPCHK(hipGraphLaunch(pl->gexec, st), "hipGraphLaunch");
+    it = first_check;
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (reinterpret_cast<volatile int&>(pl->h_ctrl->done)) it = pl->max_iter + 1;  // finished inside the graph
+  } else {
+    rc = begin_solve(pl, d_u0, d_U, w, st, pl->h_ctrl);
+    if (rc) return rc;
+  }
   for (; it < pl->max_iter; ++it) {
     hipEvent_t* evs = timing ? &pl->ev[EV_PER_IT * it] : nullptr;
     rc = enqueue_any(pl, d_u0, d_U, w, st, evs, bcast && it == 0, pl->h_ctrl);

@@ -179,3 +179,32 @@ def test_unrefined_fp32_plateau(case):
         f"(updates {['%.1e' % x for x in rep['upd_hist']]}); refined {err_r:.2e}")
     assert rep["status"] == 0 and err <= NOREFINE_BOUND
     assert repr_["status"] == 0 and err_r <= TOL
+
+
+def test_solve_graph_replays_match_direct_solves():
+    # PINT_FLAG_SOLVE_GRAPH: the first solves capture (the second one again,
+    # once the iteration count is learned), later ones replay; every replay,
+    # with new data in the same buffers and eager work in between, must equal
+    # the directly launched solve bit for bit
+    p = Problem(op="linear_ch", dim=2, n=64, nt=64, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)
+    sg = Solver.for_problem(p, precision="mixed", graph=True, device=dev())
+    sd = Solver.for_problem(p, precision="mixed", device=dev())
+    side = torch.cuda.Stream(device=dev())
+    rng = np.random.default_rng(23)
+    with torch.cuda.stream(side):
+        u0 = torch.empty(p.slice_shape, dtype=torch.float64, device=dev())
+        Ug = torch.empty(p.shape, dtype=torch.float64, device=dev())
+        scratch = torch.zeros(1 << 20, device=dev())
+        for k in range(5):
+            u0h = rng.uniform(-0.05, 0.05, p.slice_shape)
+            u0.copy_(torch.from_numpy(u0h).to(dev()))
+            _, rg = sg.solve(u0, Ug)
+            Ugh = host(Ug)
+            Ud, rd = sd.solve(u0)
+            scratch.mul_(1.5).add_(1.0)  # eager work between replays
+            torch.cuda.synchronize()
+            say(f"  solve {k}: graph iterations {rg['iterations']}, direct {rd['iterations']}")
+            assert rg["status"] == 0 and rg["iterations"] == rd["iterations"]
+            assert np.array_equal(Ugh, host(Ud))
+            if k in (0, 4):
+                assert stepper.rel_err(Ugh, stepper.sequential(p, u0h)) <= TOL
