@@ -74,6 +74,9 @@ extern "C" {
                                       FP32 accumulate (time path AUTO or DENSE);
                                       forward spatial DCT FP64 as for MIXED,
                                       inverse FP32; residual+update FP64      */
+#define PINT_PREC_BF16_NOREFINE 5  /* the unrefined FP32 loop of FP32_NOREFINE
+                                      with the BF16 dense time contraction (time
+                                      path AUTO or DENSE); stops on its plateau */
 #define PINT_PREC_MIXED         4  /* forward spatial DCT in FP64 (its rounding
                                       would be amplified by the stiffness ratio
                                       of the shifted spatial solves), time solve
@@ -161,8 +164,9 @@ const char* pint_version(void);
  * alpha == 0 selects alpha automatically (1e-3, reduced until
  * alpha * R^{N_t} <= 0.1 with R^{N_t} = (1 + dt mu_min)^{-N_t}, the
  * admissibility of thm3/thm6); an explicit alpha with alpha * R^{N_t} >= 1/2
- * is rejected with PINT_EINVAL.  The plan owns its small device tables
- * (< 1 MB); bulk memory is the caller's workspace.  *out receives the plan.
+ * is rejected with PINT_EINVAL.  The plan owns its device tables (< 1 MB,
+ * plus 8 N_t^2 bytes for the dense time path's matrices); bulk memory is the
+ * caller's workspace.  *out receives the plan.
  */
 int pint_plan_create(const pint_problem* p, pint_plan** out);
 /* Free a plan and its device tables.  NULL is accepted. */
@@ -186,9 +190,12 @@ int pint_plan_alpha(const pint_plan* plan, double* alpha);
  *   d_work  device workspace of >= pint_plan_workspace_size bytes, 256-byte
  *           aligned; contents on entry are ignored.
  *   rep     optional report (NULL allowed); rep->struct_size must be set.
- * The call enqueues on `stream` and synchronizes with it once per outer
- * iteration to read the 4-byte stop flag; it returns after the last iteration
- * has completed on the device.
+ * The call enqueues on `stream` as many iterations as the previous solve of
+ * the plan needed (kernels return at once after the device stop flag is set),
+ * synchronizes, and then once per further iteration; the control kernel
+ * writes its status to pinned host memory, so no copy is needed.  It returns
+ * after the last iteration has completed on the device.  A non-NULL stream is
+ * faster than the legacy default stream.
  */
 int pint_solve(pint_plan* plan, const double* d_u0, double* d_U, void* d_work, size_t work_bytes,
                void* stream, pint_report* rep);

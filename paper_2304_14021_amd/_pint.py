@@ -19,7 +19,7 @@ PINT_ECANCELED = -7
 PINT_ENOTFOUND = -8
 
 OPS = {"biharmonic": 0, "linear_ch": 1, "ch": 2, "ch_eyre": 3}
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3, "mixed": 4, "bf16x3": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_norefine": 2, "bf16": 3, "mixed": 4, "bf16x3": 3, "bf16_norefine": 5}
 TIME_PATHS = {"auto": 0, "fft": 1, "dense": 2}
 FLAG_INIT_BROADCAST_U0 = 0x1
 FLAG_STAGE_TIMING = 0x2

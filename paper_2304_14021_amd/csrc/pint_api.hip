@@ -132,7 +132,8 @@ double mu_min(const pint_problem& p, int dim, int n, double h) {
 
 // Kind of dense time contraction a problem asks for (-1: the FFT path).
 int dense_kind_of(const pint_problem* p) {
-  if (p->precision == PINT_PREC_BF16_REFINE) return (p->flags & PINT_FLAG_BF16_SPLIT) ? DK_BF16X3 : DK_BF16;
+  if (p->precision == PINT_PREC_BF16_REFINE || p->precision == PINT_PREC_BF16_NOREFINE)
+    return (p->flags & PINT_FLAG_BF16_SPLIT) ? DK_BF16X3 : DK_BF16;
   if (p->time_path == PINT_TIME_DENSE) return DK_F32;
   return -1;
 }
@@ -156,7 +157,8 @@ int validate(const pint_problem* p, std::string* err) {
   if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
   if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
   if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED &&
-      p->precision != PINT_PREC_BF16_REFINE && p->precision != PINT_PREC_FP32_NOREFINE)
+      p->precision != PINT_PREC_BF16_REFINE && p->precision != PINT_PREC_FP32_NOREFINE &&
+      p->precision != PINT_PREC_BF16_NOREFINE)
     return set_err(err, PINT_EINVAL, "precision not supported by this build");
   if (p->precision == PINT_PREC_FP32_NOREFINE && p->time_path == PINT_TIME_DENSE)
     return set_err(err, PINT_EINVAL, "the unrefined mode uses the FFT time path");
@@ -164,7 +166,8 @@ int validate(const pint_problem* p, std::string* err) {
     return set_err(err, PINT_EINVAL, "unknown time path");
   if (p->precision == PINT_PREC_FP64 && p->time_path == PINT_TIME_DENSE)
     return set_err(err, PINT_EINVAL, "the dense time contraction computes in FP32 or BF16, not FP64");
-  if (p->precision == PINT_PREC_BF16_REFINE && p->time_path == PINT_TIME_FFT)
+  if ((p->precision == PINT_PREC_BF16_REFINE || p->precision == PINT_PREC_BF16_NOREFINE) &&
+      p->time_path == PINT_TIME_FFT)
     return set_err(err, PINT_EINVAL, "BF16 is a precision of the dense time contraction, not of the FFT path");
   if (dense_kind_of(p) >= 0) {
     const int nb = dense_cols_per_block(p->nt);
@@ -596,7 +599,7 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   // BF16 keeps the FP64 forward spatial transform of the mixed mode
   pl->mixed = p->precision == PINT_PREC_MIXED || p->precision == PINT_PREC_BF16_REFINE;
   pl->dense = dense_kind_of(p);
-  pl->norefine = p->precision == PINT_PREC_FP32_NOREFINE;
+  pl->norefine = p->precision == PINT_PREC_FP32_NOREFINE || p->precision == PINT_PREC_BF16_NOREFINE;
   pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
   pl->nbl_f = rows_fwd_blocks_per_level(pl->dim, pl->n);
   if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {

@@ -208,3 +208,18 @@ def test_solve_graph_replays_match_direct_solves():
             assert np.array_equal(Ugh, host(Ud))
             if k in (0, 4):
                 assert stepper.rel_err(Ugh, stepper.sequential(p, u0h)) <= TOL
+
+
+def test_unrefined_bf16_plateau():
+    # The unrefined loop with the BF16 dense time contraction (reading R24):
+    # its plateau against the FP64 oracle at C2 stays under the stated 3e-2
+    # (BF16 runs take alpha = 1e-2, the BF16 default of reading R12).
+    import dataclasses
+    p = dataclasses.replace(CONFIGS["c2"], alpha=1e-2)
+    u0 = initial_datum("c2")
+    ref = stepper.sequential(p, u0)
+    U, rep, _ = _run(p, u0, "bf16_norefine")
+    err = stepper.rel_err(U, ref)
+    say(f"  c2 bf16 unrefined plateau {err:.2e} after {rep['iterations']} iterations "
+        f"(updates {['%.1e' % x for x in rep['upd_hist']]})")
+    assert rep["status"] == 0 and err <= 3e-2
