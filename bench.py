@@ -40,6 +40,7 @@ PREC_DESC = {
             "DCT, FP64 update",
     "bf16x3": "as bf16 with a two-term BF16 split of both operands (three products)",
     "fp32_norefine": "FP32 residual, transforms and iterate, no refinement (stops on its plateau)",
+    "bf16_norefine": "as fp32_norefine with the BF16 dense time contraction",
 }
 
 WORKLOADS = {
@@ -403,7 +404,7 @@ def main():
         # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
         bf16_alpha = 4e-3 if name == "c5" else BF16_ALPHA
         variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", bf16_alpha),
-                     ("bf16", "dense", bf16_alpha)]
+                     ("bf16", "dense", bf16_alpha), ("bf16_norefine", "dense", bf16_alpha)]
         for prec, tp, al in variants:
             key = prec if tp == "fft" else f"{prec}_dense"
             elo, _, repso, Uo = run(prec, args.steps, args.warmup, False, tp, al)
