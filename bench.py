@@ -245,6 +245,60 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
     return out
 
 
+def shard_bench(dev, name, precision, ranks, solves):
+    """Per-iteration kernel times at one rank's share of a P-rank run, on one
+    GPU.  The row and column passes are independent per time level, so a rank
+    runs them on nt/P levels of the full grid; the time solve is independent
+    per spatial mode, so a rank runs it on N_s/P modes over all nt levels (a
+    (n/sqrt(P))^2 grid: P a power of 4).  The exchange between the two layouts
+    is not run.  Prints one JSON line."""
+    import torch
+    from paper_2304_14021_amd import Solver
+    from workloads import CONFIGS, initial_datum, u0_uniform
+
+    p = CONFIGS[name]
+    r = int(round(ranks ** 0.5))
+    if ranks < 4 or r * r != ranks or p.nt % ranks or p.n % r or p.dim != 2:
+        raise SystemExit(f"--shard needs a 2D workload and a power of 4 that divides nt and n^2 (got {ranks})")
+    level_shard = dataclasses.replace(p, nt=p.nt // ranks)
+    mode_shard = dataclasses.replace(p, n=p.n // r)
+    side = torch.cuda.Stream(device=dev)
+
+    def per_iteration(q, u0_h):
+        s = Solver.for_problem(q, precision=precision, device=dev, stage_timing=True)
+        u0 = torch.from_numpy(u0_h).to(dev)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            U = torch.empty(q.shape, dtype=torch.float64, device=dev)
+            # per-iteration times only: a shard shape need not reach the stop rule
+            s.solve(u0, U, raise_on_error=False)
+            reps = [s.solve(u0, U, raise_on_error=False)[1] for _ in range(solves)]
+        torch.cuda.synchronize()
+        its = sum(x["iterations"] for x in reps)
+        out = {st: sum(x["ms_stage"][i] for x in reps) / its for i, st in enumerate(STAGES)}
+        del s, U
+        torch.cuda.empty_cache()
+        return out, its / len(reps)
+
+    full, it_full = per_iteration(p, initial_datum(name))
+    lev, it_lev = per_iteration(level_shard, initial_datum(name))
+    mode, it_mode = per_iteration(mode_shard, u0_uniform((mode_shard.n,) * 2, 0.05, 5))
+    stages = {}
+    for st in STAGES:
+        shard_ms = mode[st] if st == "time_solve" else lev[st]
+        stages[st] = {"full_ms": full[st], "full_over_ranks_ms": full[st] / ranks, "shard_ms": shard_ms}
+    log(f"{name} {precision}: iterations full {it_full:.1f}, level shard {it_lev:.1f}, mode shard {it_mode:.1f}")
+    for st, v in stages.items():
+        log(f"  {st:10s} full {v['full_ms'] * 1e3:9.1f} us  full/P {v['full_over_ranks_ms'] * 1e3:8.1f} us  "
+            f"shard {v['shard_ms'] * 1e3:8.1f} us")
+    print(json.dumps({
+        "metric": "per-iteration kernel time at one rank's shard shape (exchange not run)",
+        "unit": "ms", "ranks": ranks, "dtype": "f64" if precision == "fp64" else "f64+f32",
+        "config": {"workload": WORKLOADS[name], "precision": precision,
+                   "level_shard": list(level_shard.shape), "mode_shard": list(mode_shard.shape)},
+        "stages": stages}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +315,8 @@ def main():
     ap.add_argument("--serve-no-graphs", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device-to-device copy launched before the steps (counter calibration)")
+    ap.add_argument("--shard", type=int, default=0,
+                    help="time each kernel at one rank's share of a run on this many GPUs (a power of 4) instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -276,6 +332,9 @@ def main():
     name = args.config
     p = CONFIGS[name]
     dev = torch.device("cuda:0")
+    if args.shard:
+        shard_bench(dev, name, args.precision, args.shard, max(1, min(args.steps, 5)))
+        return
     u0_h = initial_datum(name)
     u0 = torch.from_numpy(u0_h).to(dev)
 
