@@ -5,6 +5,8 @@ Bar: relative error max_n ||u_n - u_n^ref||_2 / max_n ||u_n^ref||_2 <= 1e-10
 for the FP64 and the FP32-refined paths (the paper's stopping tolerance,
 Section 5, measured in its L^inf(0,T;L^2) norm).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -49,6 +51,20 @@ def test_c2_linear_ch_2d_full_size(prec):
     say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
     assert rep["status"] == 0 and err <= TOL
     assert stepper.rel_err_inf(U, ref) <= 10 * TOL
+
+
+def test_c2_small_alpha_two_steps():
+    """Very small alpha: the linearized CH solve is done in two outer
+    iterations (the two-step convergence the paper reports for small alpha in
+    its linearized CH experiments, Section 6).  FP64 at alpha = 1e-6: the
+    first step leaves an error of order alpha, the second of order alpha^2."""
+    say("c2 fp64 alpha 1e-6")
+    p = dataclasses.replace(CONFIGS["c2"], alpha=1e-6)
+    u0 = initial_datum("c2")
+    U, rep, _ = _run(p, u0, "fp64")
+    err = stepper.rel_err(U, stepper.sequential(p, u0))
+    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
+    assert rep["status"] == 0 and rep["iterations"] == 2 and err <= TOL
 
 
 SOLVE_CASES = [
