@@ -143,7 +143,7 @@ def _spin_until(t_target):
             time.sleep(d - 1e-3)
 
 
-def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, graphs=True):
+def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, graphs=True, alpha=0.0):
     """The served stream through the library's serving loop.
 
     Closed loop: all requests queued at once; the saturation rate is requests
@@ -160,6 +160,8 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
     from workloads import request_u0, served_stream
 
     reqs = served_stream(n_requests=n_requests, seed=4, rate=1.0)
+    if alpha:
+        reqs = [dataclasses.replace(r, problem=dataclasses.replace(r.problem, alpha=alpha)) for r in reqs]
     u0h = [request_u0(r) for r in reqs]
     u0d = [torch.from_numpy(u).to(dev) for u in u0h]
     Ud = [torch.empty(r.problem.shape, dtype=torch.float64, device=dev) for r in reqs]
@@ -206,7 +208,7 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
             d["arrival_rate_req_per_s"] = rate
         return d
 
-    out = {"workload": SERVED, "precision": PREC_DESC[precision], "slots": slots, "pool_bytes": pool,
+    out = {"workload": SERVED, "precision": PREC_DESC[precision], "alpha": alpha or reqs[0].problem.alpha, "slots": slots, "pool_bytes": pool,
            "graphs": graphs,
            "io": "device-resident (u0 and U in HBM)"}
     with Server(pool, max_active=slots, graphs=graphs, device=dev) as srv:
@@ -320,7 +322,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-precision", default="mixed", choices=["mixed", "fp32", "fp64"])
+    # served requests: FP64 at alpha = 1e-6 (two outer iterations each, as the headline)
+    ap.add_argument("--serve-precision", default="fp64", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--serve-alpha", type=float, default=1e-6, help="alpha of every served request (0: the stream's)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -511,7 +515,8 @@ def main():
             out["paths"][key] = d
     if not args.no_serving:
         out["serving"] = serving_bench(dev, args.serve_precision, args.serve_slots, args.serve_pool_gib,
-                                       args.serve_requests, oracle_checks=8, graphs=not args.serve_no_graphs)
+                                       args.serve_requests, oracle_checks=8, graphs=not args.serve_no_graphs,
+                                       alpha=args.serve_alpha)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)

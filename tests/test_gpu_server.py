@@ -239,3 +239,18 @@ def test_served_dense_bf16_requests():
         assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
         assert np.array_equal(U, ref)
         assert stepper.rel_err(U, stepper.sequential(p, u0)) <= 1e-10
+
+
+def test_served_fp64_small_alpha_two_steps():
+    # the benchmark's served configuration: FP64 requests at alpha = 1e-6 take
+    # two outer iterations each and meet the 1e-10 bar against the oracle
+    reqs = served_stream(n_requests=6, seed=11, grids=(64, 128), nts=(32, 64, 128))
+    reqs = [dataclasses.replace(r, problem=dataclasses.replace(r.problem, alpha=1e-6)) for r in reqs]
+    with Server(1 << 30, max_active=3, device=dev()) as srv:
+        res = [srv.wait(t, timeout_ms=120000) for t in
+               [srv.submit(r.problem, request_u0(r), precision="fp64") for r in reqs]]
+    for i, (r, (U, rep)) in enumerate(zip(reqs, res)):
+        err = stepper.rel_err(U, stepper.sequential(r.problem, request_u0(r)))
+        say(f"  request {i} {r.problem.op} n{r.problem.n} nt{r.problem.nt} fp64 alpha 1e-6: "
+            f"it {rep['iterations']} err {err:.2e}")
+        assert rep["status"] == 0 and rep["iterations"] == 2 and err <= 1e-10
