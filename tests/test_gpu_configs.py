@@ -12,6 +12,7 @@ C5: 2D CH (PinT-I), eps = 0.0075, 512^2 cells, 1024 levels, dt = 1e-6,
     own previous level at sampled levels, plus exact mass conservation and a
     non-increasing energy.
 """
+import dataclasses
 import json
 import os
 
@@ -29,8 +30,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_samples.json")
 
 
-def _solve(name, prec):
-    p = CONFIGS[name]
+def _solve(name, prec, alpha=None):
+    p = CONFIGS[name] if alpha is None else dataclasses.replace(CONFIGS[name], alpha=alpha)
     u0 = initial_datum(name)
     s = Solver.for_problem(p, precision=prec, device=dev())
     Ud, rep = s.solve(to_dev(u0), raise_on_error=False)
@@ -38,11 +39,13 @@ def _solve(name, prec):
     return p, u0, host(Ud), rep, host(m), host(e)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
-def test_c3_against_oracle_samples(prec):
-    say(f"c3 {prec}")
+# alpha = 1e-4: one outer iteration fewer than at the workload's 1e-3 (the
+# benchmark's choice for the nonlinear CH workloads)
+@pytest.mark.parametrize("prec,alpha", [("mixed", None), ("fp64", None), ("fp32", None), ("mixed", 1e-4)])
+def test_c3_against_oracle_samples(prec, alpha):
+    say(f"c3 {prec} alpha {alpha}")
     g = json.load(open(GOLDEN))
-    p, u0, U, rep, m, e = _solve("c3", prec)
+    p, u0, U, rep, m, e = _solve("c3", prec, alpha)
     say(f"  status {rep['status']} iterations {rep['iterations']} updates {['%.1e' % x for x in rep['upd_hist']]}")
     assert rep["status"] == 0
     norms = np.sqrt(np.sum(U.reshape(p.nt, -1) ** 2, axis=1))
@@ -64,10 +67,10 @@ def test_c3_against_oracle_samples(prec):
     assert np.all(np.diff(e_all) <= 1e-13 * np.abs(e_all[1:]))
 
 
-@pytest.mark.parametrize("prec", ["mixed"])
-def test_c5_steps_mass_energy(prec):
-    say(f"c5 {prec}")
-    p, u0, U, rep, m, e = _solve("c5", prec)
+@pytest.mark.parametrize("prec,alpha", [("mixed", None), ("mixed", 1e-4)])
+def test_c5_steps_mass_energy(prec, alpha):
+    say(f"c5 {prec} alpha {alpha}")
+    p, u0, U, rep, m, e = _solve("c5", prec, alpha)
     say(f"  status {rep['status']} iterations {rep['iterations']} updates {['%.1e' % x for x in rep['upd_hist']]}")
     assert rep["status"] == 0
     # Necessary condition of a 1e-10 relative L^inf(L^2) error: each level
