@@ -47,6 +47,21 @@ def circulant_blocks(nt: int, dt: float, theta: float, alpha: float):
     return c1, c2
 
 
+def step_blocks(dts, theta: float = 1.0):
+    """Time-step matrices of the theta-method with nonuniform steps dt_n
+    (alpha = 0): B = diag(1/dt_n) (I - S) and C = theta I + (1 - theta) S,
+    S the down-shift, so that the scheme over all levels reads
+    (B (x) I + C (x) A) U = b.  With equal steps B = C1^(0) and C = C2^(0)
+    of eq. ciculantmat.  Unlike C1^(alpha), B is not alpha-circulant; it is
+    diagonalized directly (Section 1: direct diagonalization with variable
+    steps)."""
+    dts = np.asarray(dts, dtype=np.float64)
+    nt = dts.size
+    b = (np.eye(nt) - np.eye(nt, k=-1)) / dts[:, None]
+    c = theta * np.eye(nt) + (1.0 - theta) * np.eye(nt, k=-1)
+    return b, c
+
+
 def c3_block(nt: int, alpha: float):
     """C3 = C2 with theta = 0 (Section 4.1, after eq. all-at-once_CH_Eyre)."""
     _, c3 = circulant_blocks(nt, 1.0, 0.0, alpha)
@@ -74,6 +89,23 @@ def rhs_linear(u0: np.ndarray, a: sp.spmatrix, nt: int, dt: float, theta: float,
     return b
 
 
+def allatonce_matrix_steps(a: sp.spmatrix, dts, theta: float) -> sp.csr_matrix:
+    """B (x) I + C (x) A for nonuniform steps (``step_blocks``)."""
+    b, c = step_blocks(dts, theta)
+    eye = sp.identity(a.shape[0], format="csr")
+    return (sp.kron(sp.csr_matrix(b), eye) + sp.kron(sp.csr_matrix(c), a)).tocsr()
+
+
+def rhs_steps(u0: np.ndarray, a: sp.spmatrix, dts, theta: float) -> np.ndarray:
+    """First block u0/dt_1 - (1-theta) A u0, the others zero."""
+    dts = np.asarray(dts, dtype=np.float64)
+    ns = a.shape[0]
+    w = np.asarray(u0, dtype=np.float64).reshape(-1)
+    b = np.zeros(dts.size * ns)
+    b[:ns] = w / dts[0] - (1.0 - theta) * (a @ w)
+    return b
+
+
 # ------------------------------------------------------------------ residuals
 def residual_linear(p, U: np.ndarray, u0: np.ndarray) -> np.ndarray:
     """True alpha = 0 residual r = b_0 - (C1^(0) (x) I + C2^(0) (x) A) U of the
@@ -83,6 +115,29 @@ def residual_linear(p, U: np.ndarray, u0: np.ndarray) -> np.ndarray:
     k = allatonce_matrix(a, p.nt, p.dt, p.theta, 0.0)
     b = rhs_linear(u0, a, p.nt, p.dt, p.theta)
     return (b - k @ U.reshape(-1)).reshape(U.shape)
+
+
+def residual_steps(p, U: np.ndarray, u0: np.ndarray, dts) -> np.ndarray:
+    """True residual r = b - K(U) of the sequential scheme with nonuniform
+    steps (linear: (B (x) I + C (x) A); CH: eq. nonlinear_G with 1/dt_n in
+    the time difference of level n), all levels."""
+    dts = np.asarray(dts, dtype=np.float64)
+    if p.op in ("biharmonic", "linear_ch"):
+        a = ops.operator_a(p.op, p.dim, p.n, p.h, eps=p.eps, beta=p.beta)
+        k = allatonce_matrix_steps(a, dts, p.theta)
+        return (rhs_steps(u0, a, dts, p.theta) - k @ U.reshape(-1)).reshape(U.shape)
+    lap = ops.laplacian(p.dim, p.n, p.h)
+    e2 = p.eps * p.eps
+    out = []
+    for n in range(1, p.nt + 1):
+        un = U[n - 1].reshape(-1)
+        um = (u0 if n == 1 else U[n - 2]).reshape(-1)
+        if p.op == "ch":
+            g = (un - um) / dts[n - 1] - lap @ (un ** 3) + lap @ un + e2 * (lap @ (lap @ un))
+        else:
+            raise ValueError(f"nonuniform steps: no residual for {p.op}")
+        out.append(-g)
+    return np.array(out).reshape(U.shape)
 
 
 def residual_linear_levels(p, U: np.ndarray, u0: np.ndarray, levels) -> np.ndarray:
@@ -243,6 +298,27 @@ def time_solve_modal(p, rh: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
     else:
         raise ValueError(p.op)
     sol = np.linalg.solve(mats, x.T[:, :, None])[:, :, 0]   # [modes][nt]
+    return sol.T.reshape(rh.shape)
+
+
+def time_solve_steps_modal(p, rh: np.ndarray, dts, c_bar: float = 0.0) -> np.ndarray:
+    """The space-time solve with nonuniform backward-Euler steps in the cosine
+    basis: per spatial mode k the dense N_t x N_t system (B + mu_k I) y = x
+    (linear; theta = 1), or (B + ((1 - c_bar) lam_k + eps^2 lam_k^2) I) y = x
+    (CH with the scalar averaged Jacobian), solved by numpy.linalg.solve --
+    no eigendecomposition."""
+    nt = p.nt
+    x = rh.reshape(nt, -1)
+    lam, mu = spatial_symbols(p)
+    b, _ = step_blocks(dts, 1.0)
+    if p.op in ("biharmonic", "linear_ch"):
+        shift = mu
+    elif p.op == "ch":
+        shift = (1.0 - c_bar) * lam + p.eps ** 2 * lam * lam
+    else:
+        raise ValueError(p.op)
+    mats = b[None] + shift[:, None, None] * np.eye(nt)[None]
+    sol = np.linalg.solve(mats, x.T[:, :, None])[:, :, 0]
     return sol.T.reshape(rh.shape)
 
 

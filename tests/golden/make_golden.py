@@ -1,12 +1,20 @@
-"""Write tests/golden/c3_samples.json from the CPU oracle only.
+"""Write tests/golden/<config>_samples.json from the CPU oracle only.
 
-Configuration: 2D nonlinear CH (fully implicit backward Euler), eps = 0.01,
-256 x 256 cells on the unit square, 256 levels, dt = 1e-6, u0 ~ U[-0.1, 0.1]
-(seed 3).  Stored: per-level ||u_n||_2, mass and Ginzburg-Landau energy, and
-u_n at 64 seeded sample points for 8 levels.  The full solution (134 MB) is
-not stored; tests compare the GPU solve against these samples.
+Configurations (2D nonlinear CH, fully implicit backward Euler, unit square,
+Neumann; seeded u0 from ``workloads``):
+  c3  eps = 0.01,   256 x 256 cells, 256 levels,  dt = 1e-6, u0 ~ U[-0.1, 0.1]   (~2 min)
+  c5  eps = 0.0075, 512 x 512 cells, 1024 levels, dt = 1e-6, u0 ~ U[-0.05, 0.05] (~1 h)
 
-Run:  python tests/golden/make_golden.py   (about 3 minutes on one core)
+Stored for every level n = 1..N_t:
+  * ||u_n||_2, the discrete mass and the Ginzburg-Landau energy;
+  * four projections <w_q, u_n> on seeded standard-normal weight arrays w_q
+    (numpy default_rng(PROJ_SEED + q), shape of one level) -- an error anywhere
+    in a level moves them by about its own size, so together with the norms
+    they check every level of a solve, not only sampled points;
+and u_n itself at 256 seeded points for 16 levels.  The full solution (up to
+2.1 GB) is not stored.
+
+Run:  python tests/golden/make_golden.py c3|c5
 """
 import json
 import os
@@ -22,7 +30,21 @@ from oracle import operators as ops  # noqa: E402
 from oracle import stepper  # noqa: E402
 from workloads import CONFIGS, initial_datum  # noqa: E402
 
-LEVELS = [1, 2, 8, 32, 64, 128, 200, 256]
+PROJ_SEED = 4321
+N_PROJ = 4
+N_POINTS = 256
+
+
+def sample_levels(nt: int):
+    """About 16 levels spread over 1..nt (geometric near the start, where the
+    solution changes fastest, and uniform), the first and the last included."""
+    geo = np.round(np.geomspace(1, nt, 10)).astype(int).tolist()
+    lin = np.linspace(1, nt, 8).astype(int).tolist()
+    return sorted(set(geo + lin))
+
+
+def projection_weights(shape):
+    return [np.random.default_rng(PROJ_SEED + q).standard_normal(shape) for q in range(N_PROJ)]
 
 
 def main(name="c3"):
@@ -32,25 +54,31 @@ def main(name="c3"):
     U, iters = stepper.ch_implicit(p.dim, p.n, p.nt, p.dt, u0, p.eps, return_iters=True)
     el = time.time() - t0
     rng = np.random.default_rng(1234)
-    pts = rng.integers(0, p.n, size=(64, 2))
+    pts = rng.integers(0, p.n, size=(N_POINTS, 2))
+    levels = sample_levels(p.nt)
+    ws = projection_weights(p.slice_shape)
     out = {
         "config": name,
         "problem": {"op": p.op, "dim": p.dim, "n": p.n, "nt": p.nt, "dt": p.dt, "eps": p.eps},
-        "oracle": "sequential backward-Euler CH, banded-Cholesky chord iterations to 1e-14",
+        "oracle": "sequential backward-Euler CH, banded-Cholesky chord iterations until the increment "
+                  "and dt ||F||_inf are below 1e-14",
         "oracle_seconds": round(el, 1),
         "chord_iterations_max": int(max(iters)),
+        "chord_iterations_total": int(sum(iters)),
         "norms": [float(np.sqrt(np.sum(u * u))) for u in U],
         "mass": [ops.mass(u, p.h) for u in U],
         "energy": [ops.energy(u, p.eps, p.h) for u in U],
         "energy0": ops.energy(u0, p.eps, p.h),
         "mass0": ops.mass(u0, p.h),
+        "proj_seed": PROJ_SEED,
+        "projections": [[float(np.sum(w * u)) for w in ws] for u in U],
         "points": pts.tolist(),
-        "samples": {str(n): [float(U[n - 1][y, x]) for y, x in pts] for n in LEVELS},
+        "samples": {str(n): [float(U[n - 1][y, x]) for y, x in pts] for n in levels},
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_samples.json")
     with open(path, "w") as f:
         json.dump(out, f)
-    print(f"wrote {path} ({el:.0f} s oracle)")
+    print(f"wrote {path} ({el:.0f} s oracle, chord iterations {min(iters)}-{max(iters)})")
 
 
 if __name__ == "__main__":
