@@ -3,12 +3,15 @@
 One step = one complete solve (every stage of the hot path: FP64 residual +
 DCT-II, alpha-circulant time FFT solve, DCT-III + FP64 update, reductions and
 stop rule, repeated until the estimated relative error is below 1e-10) of the
-2D linearized Cahn-Hilliard workload (128 x 128 cells, 128 backward-Euler
-levels, dt = 1e-5, beta = 0.5, eps = 0.05, u0 ~ U[-0.05, 0.05] seeded),
-inputs resident in HBM; FP64 throughout with alpha = 1e-6 (two outer
-iterations), the other precisions and alphas reported beside it.  The metric
-is space-time DOF/s = N_s N_t / solve time, with the result checked against
-the CPU FP64 oracle.  Prints one JSON line.
+largest single-GPU workload: 2D nonlinear Cahn-Hilliard (PinT-I), 512 x 512
+cells, 1024 backward-Euler levels, dt = 1e-6, eps = 0.0075,
+u0 ~ U[-0.05, 0.05] seeded, inputs resident in HBM; refined mixed precision
+(FP64 residual, forward DCT and update; FP32 time solve and inverse DCT) with
+alpha = 1e-4.  Plain FP64, the other precisions and the dense matrix-core time
+contraction are timed beside it.  The metric is space-time DOF/s = N_s N_t /
+solve time; the result is checked against stored data of the CPU FP64
+oracle's sequential solution (tests/golden).  ``--config c2|c3`` selects the
+smaller workloads.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -50,21 +53,21 @@ PREC_DESC = {
 WORKLOADS = {
     "c2": "2D linearized CH u_t = -beta^2 Lap u - eps^2 Lap^2 u, beta=0.5, eps=0.05, unit square, Neumann, "
           "128x128 cells x 128 backward-Euler levels, dt=1e-5, u0 ~ U[-0.05,0.05] (seed 2)",
-    "c1": "1D biharmonic heat, 64 cells x 32 backward-Euler levels, T=1e-3, u0=cos(pi x)+0.5cos(3 pi x)+1e-3 N(0,1)",
     "c3": "2D nonlinear CH (PinT-I), f(u)=u^3-u, eps=0.01, unit square, Neumann, 256x256 cells x 256 levels, dt=1e-6, "
           "u0 ~ U[-0.1,0.1] (seed 3)",
     "c5": "2D nonlinear CH (PinT-I), eps=0.0075, unit square, Neumann, 512x512 cells x 1024 levels, dt=1e-6, "
           "u0 ~ U[-0.05,0.05] (seed 5)",
 }
-# Configurations whose sequential oracle finishes in seconds are checked
-# against it here; the larger ones are checked by the GPU tests (stored oracle
-# samples for 256^2 x 256, oracle single steps for 512^2 x 1024) and report
-# mass conservation and energy decay here.
-ORACLE_IN_BENCH = ("c1", "c2")
+# Every workload is checked against stored data of the oracle's sequential
+# solution (tests/golden/<config>_samples.json, written by
+# tests/golden/make_golden.py from the oracle only): per-level norms and
+# random projections at every level, and points at sampled levels.  The
+# oracle itself runs here only in the cpu_baseline leg.
+GOLDEN = ("c2", "c3", "c5")
 # Headline precision and alpha per workload (others: mixed at the workload's
 # alpha).  At 128^2 x 128 the FP64 path with alpha = 1e-6 reaches the 1e-10
 # bar in two outer iterations (the small-alpha two-step convergence of the
-# linearized CH experiments, Section 6); the FP32 paths cannot use so small an
+# linearized CH experiments, Section 5); the FP32 paths cannot use so small an
 # alpha, since their rounding error per iteration grows like u_32 / alpha.
 # The nonlinear CH workloads are limited by the scalar averaged Jacobian, not
 # alpha; there alpha = 1e-4 saves one (256^2 x 256) to five (512^2 x 1024)
@@ -99,22 +102,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Levels of the oracle's sequential solve timed by the CPU baseline when a
+# whole solve takes minutes or more (about 10-30 s of host work).
+CPU_PREFIX_LEVELS = {"c3": 64, "c5": 8}
+
+
 def cpu_baseline(name: str, min_seconds: float = 10.0):
     """The oracle (sequential FP64 backward Euler with banded Cholesky) timed
-    on the host on whole solves of the same workload until min_seconds pass."""
+    on the host on the same workload: whole solves until min_seconds pass, or
+    for the large workloads the first levels of the sequential solve (its
+    factorization included), in DOF of the levels solved per second."""
     import numpy as np
     from oracle import stepper
     from workloads import CONFIGS, initial_datum
     p = CONFIGS[name]
     u0 = initial_datum(name)
+    levels = CPU_PREFIX_LEVELS.get(name)
+    q = dataclasses.replace(p, nt=levels) if levels else p
     reps = 0
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     while True:
-        stepper.sequential(p, u0)
+        stepper.sequential(q, u0)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= min_seconds:
+        if el >= min_seconds or levels:
             break
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
@@ -123,14 +135,24 @@ def cpu_baseline(name: str, min_seconds: float = 10.0):
         blas = ",".join(f"{d.get('internal_api')}:{d.get('num_threads')}" for d in threadpool_info())
     except Exception:
         blas = "unknown"
+    what = (f"the first {levels} of {p.nt} levels of the sequential solve ({q.dof} DOF, one banded Cholesky "
+            f"factorization included)" if levels else
+            f"{reps} complete sequential solves of the same workload ({p.dof} DOF each)")
     return {
-        "value": reps * p.dof / el,
+        "value": reps * q.dof / el,
         "unit": "DOF/s",
         "cores": max(1, int(round(cpu / el))),
         "kind": "oracle",
-        "sample": f"{reps} complete sequential solves of the same workload ({p.dof} DOF each) in {el:.1f} s; "
-                  f"host CPU time / wall = {cpu / el:.2f}; os.cpu_count()={os.cpu_count()}; BLAS {blas}",
+        "sample": f"{what} in {el:.1f} s; host CPU time / wall = {cpu / el:.2f}; os.cpu_count()={os.cpu_count()}; "
+                  f"BLAS {blas}",
     }
+
+
+def golden_deviation(name: str, U) -> dict:
+    """Deviation of a GPU result from the stored oracle data of the workload
+    (relative to max_n ||u_n^ref||_2; 'rel' <= 1e-10 is the paper's bar)."""
+    from tests import _golden
+    return _golden.compare(U.cpu().numpy() if hasattr(U, "cpu") else U, _golden.load(name))
 
 
 SERVED = ("c4: 512 Poisson-arrival requests, biharmonic heat / linearized CH 50/50, grids {64^2,128^2,256^2}, "
@@ -158,8 +180,8 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
     rate."""
     import numpy as np
     import torch
-    from oracle import stepper
     from paper_2304_14021_amd import Server, Solver
+    from tests import _golden
     from workloads import request_u0, served_stream
 
     reqs = served_stream(n_requests=n_requests, seed=4, rate=1.0)
@@ -246,15 +268,16 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
         del s
     out["one_at_a_time"] = {"dof_per_s": float(dof.sum()) / solo, "req_per_s": len(reqs) / solo,
                             "note": "sum of standalone solve times of the same requests"}
-    # served results (last device-resident pass) against the oracle, on the
-    # smallest requests
+    # served results (a fresh device-resident pass) against stored data of
+    # the oracle's sequential solutions of the smallest requests
     errs = []
+    g = _golden.load("c4")["requests"]
     with Server(pool, max_active=slots, device=dev) as srv:
-        order = np.argsort(dof)[:oracle_checks]
+        order = [int(i) for i in g][:oracle_checks]
         tk = [(i, srv.submit_device(reqs[i].problem, u0d[i], Ud[i], precision=precision)) for i in order]
         for i, t in tk:
             srv.wait(t)
-            errs.append(stepper.rel_err(Ud[i].cpu().numpy(), stepper.sequential(reqs[i].problem, u0h[i])))
+            errs.append(_golden.compare(Ud[i].cpu().numpy(), g[str(i)])["rel"])
     out["rel_err_vs_oracle_max"] = float(max(errs)) if errs else None
     out["oracle_checked_requests"] = len(errs)
     return out
@@ -317,11 +340,13 @@ def shard_bench(dev, name, precision, ranks, solves):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["mixed", "fp32", "fp64"],
                     help="headline precision (default: fp64 for c2, else mixed)")
+    ap.add_argument("--path-steps", type=int, default=5,
+                    help="solves per timed loop of the other precision paths (c5; all steps for the others)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -346,7 +371,6 @@ def main():
 
     import numpy as np
     import torch
-    from oracle import stepper
     from paper_2304_14021_amd import Solver
     from workloads import CONFIGS, initial_datum
 
@@ -378,7 +402,7 @@ def main():
     # ~5% at this size, and solve graphs need a non-default stream
     side = torch.cuda.Stream(device=dev)
 
-    def run(prec, steps, warmup, timing, time_path="auto", alpha=None, graph=False):
+    def run(prec, steps, warmup, timing, time_path="auto", alpha=None, graph=False, strict=True):
         q = p if alpha is None else dataclasses.replace(p, alpha=alpha)
         s = Solver.for_problem(q, precision=prec, device=dev, stage_timing=timing, time_path=time_path,
                                graph=graph)
@@ -386,39 +410,39 @@ def main():
         with torch.cuda.stream(side):
             U = torch.empty(p.shape, dtype=torch.float64, device=dev)
             for _ in range(warmup):
-                s.solve(u0, U)
+                s.solve(u0, U, raise_on_error=strict)
             torch.cuda.synchronize()
             lat = []
             reps = []
             t0 = time.perf_counter()
             for _ in range(steps):
                 ts = time.perf_counter()
-                _, rep = s.solve(u0, U)
+                _, rep = s.solve(u0, U, raise_on_error=strict)
                 lat.append((time.perf_counter() - ts) * 1e3)
                 reps.append(rep)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
+        del s
         return el, lat, reps, U
 
     # timed region: K complete solves, no instrumentation
     el, lat, reps, U = run(args.precision, args.steps, args.warmup, False, alpha=head_alpha)
     value = p.dof * args.steps / el
     iters = [r["iterations"] for r in reps]
-    if name in ORACLE_IN_BENCH:
-        ref = stepper.sequential(p, u0_h)
-        err = stepper.rel_err(U.cpu().numpy(), ref)
-    else:
-        ref, err = None, None
-        s_chk = Solver.for_problem(p, precision=args.precision, device=dev)
-        m, e = s_chk.diagnostics(U)
-        m, e = m.cpu().numpy(), e.cpu().numpy()
-        invariants = {"mass_drift_max": float(np.max(np.abs(m - m[0]))),
-                      "energy_nonincreasing": bool(np.all(np.diff(e) <= 1e-13 * np.abs(e[1:]))),
-                      "energy_first_last": [float(e[0]), float(e[-1])]}
-        del s_chk
+    dev_g = golden_deviation(name, U)
+    err = dev_g["rel"]
+    Uh = U.cpu().numpy()
+    # invariants of the result (Section 1): the same solve with the report's
+    # mass drift and energy monotonicity, outside the timed region
+    s_chk = Solver.for_problem(p if head_alpha is None else dataclasses.replace(p, alpha=head_alpha),
+                               precision=args.precision, device=dev, invariants=True)
+    U_chk, rep_chk = s_chk.solve(u0)
+    invariants = {"mass_drift": rep_chk["mass_drift"], "energy_monotone": rep_chk["energy_monotone"],
+                  "bitwise_equal_to_timed_result": bool(torch.equal(U_chk, U))}
+    del s_chk, U_chk
     log(f"{name} {args.precision}: {args.steps} solves in {el:.3f}s, iterations {sorted(set(iters))}, "
-        f"rel err vs oracle {err if err is None else f'{err:.2e}'}, update history {['%.1e' % x for x in reps[-1]['upd_hist']]}, "
-        f"estimate {reps[-1]['est_rel_err']:.1e}")
+        f"deviation from the stored oracle data {json.dumps(dev_g)}, update history "
+        f"{['%.1e' % x for x in reps[-1]['upd_hist']]}, estimate {reps[-1]['est_rel_err']:.1e}; {invariants}")
     # the same K solves again with HIP events recorded on the solve's stream
     # around every kernel launch (per-kernel durations; events add overhead,
     # so this loop is not the headline number)
@@ -461,14 +485,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "mixed": "f32", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f64+f32", "mixed": "f64+f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{name}: {WORKLOADS[name]}",
                    "precision": PREC_DESC[args.precision],
                    "dof": p.dof, "alpha": reps[-1]["alpha"], "rtol": 1e-10,
                    "iterations": iters[-1]},
         "rel_err_vs_oracle": err,
-        **({} if ref is not None else {"invariants": invariants}),
+        "oracle_check": {"kind": "stored oracle data (tests/golden): per-level norms and 4 random projections "
+                                 "at every level, 256 points at ~16 levels; each deviation / max_n ||u_n^ref||_2",
+                         **dev_g},
+        "invariants": invariants,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "roofline": roofline,
@@ -481,13 +508,17 @@ def main():
         # workload and step count (value loop without events; the dense
         # variants get a second loop with events for the contraction kernel)
         out["paths"] = {}
+        ps = min(args.steps, args.path_steps) if name == "c5" else args.steps
+        pw = min(args.warmup, 1) if name == "c5" else args.warmup
         # the headline path replayed from a captured solve graph (PINT_FLAG_SOLVE_GRAPH)
-        elg, _, _, _ = run(args.precision, args.steps, args.warmup, False, alpha=head_alpha, graph=True)
-        out["paths"][f"{args.precision}_solve_graph"] = {"value": p.dof * args.steps / elg,
-                                                         "ms_per_step": elg / args.steps * 1e3}
-        variants = [(o, "fft", None) for o in ("mixed", "fp32", "fp64") if o != args.precision]
+        elg, _, _, _ = run(args.precision, ps, pw, False, alpha=head_alpha, graph=True)
+        out["paths"][f"{args.precision}_solve_graph"] = {"value": p.dof * ps / elg,
+                                                         "ms_per_step": elg / ps * 1e3}
+        # every refined path at the headline's alpha, then the headline path at
+        # the workload's alpha
+        variants = [(o, "fft", head_alpha) for o in ("mixed", "fp32", "fp64") if o != args.precision]
         if head_alpha is not None and head_alpha != p.alpha:
-            variants += [(args.precision, "fft", p.alpha)]  # the headline path at the workload's alpha
+            variants += [(args.precision, "fft", p.alpha)]
         variants += [("fp32_norefine", "fft", None)]  # the unrefined plateau (not at the 1e-10 bar)
         # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
         bf16_alpha = 4e-3 if name == "c5" else BF16_ALPHA
@@ -497,14 +528,17 @@ def main():
             key = prec if tp == "fft" else f"{prec}_dense"
             if prec == args.precision and tp == "fft":
                 key = f"{prec}_alpha_{al:g}"
-            elo, _, repso, Uo = run(prec, args.steps, args.warmup, False, tp, al)
-            log(f"{key} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
-            d = {"value": p.dof * args.steps / elo, "ms_per_step": elo / args.steps * 1e3,
-                 "iterations": repso[-1]["iterations"], "alpha": repso[-1]["alpha"],
-                 "rel_err_vs_oracle": stepper.rel_err(Uo.cpu().numpy(), ref) if ref is not None else None,
-                 "rel_diff_vs_headline": stepper.rel_err(Uo.cpu().numpy(), U.cpu().numpy())}
+            elo, _, repso, Uo = run(prec, ps, pw, False, tp, al, strict=False)
+            log(f"{key} status {repso[-1]['status']} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
+            Uoh = Uo.cpu().numpy()
+            d = {"value": p.dof * ps / elo, "ms_per_step": elo / ps * 1e3, "steps": ps,
+                 "status": repso[-1]["status"], "iterations": repso[-1]["iterations"], "alpha": repso[-1]["alpha"],
+                 "rel_err_vs_oracle": golden_deviation(name, Uoh)["rel"],
+                 "rel_diff_vs_headline": float(np.max(np.sqrt(np.sum((Uoh - Uh).reshape(p.nt, -1) ** 2, axis=1)))
+                                               / np.max(np.sqrt(np.sum(Uh.reshape(p.nt, -1) ** 2, axis=1))))}
+            del Uo, Uoh
             if tp == "dense":
-                _, _, repe, _ = run(prec, args.steps, args.warmup, True, tp, al)
+                _, _, repe, _ = run(prec, ps, pw, True, tp, al, strict=False)
                 its = sum(r["iterations"] for r in repe)
                 us = sum(r["ms_stage"][2] for r in repe) / max(1, its) * 1e3
                 flops = 4.0 * p.nt * p.dof * (3 if prec == "bf16x3" else 1)

@@ -106,6 +106,10 @@ extern "C" {
 #define PINT_FLAG_BF16_SPLIT        0x4u /* PINT_PREC_BF16_REFINE: two-term BF16
                                             split of both operands, three
                                             products (hi*hi + hi*lo + lo*hi) */
+#define PINT_FLAG_INVARIANTS       0x10u /* pint_solve: after the last iteration,
+                                            fill pint_report.mass_drift and
+                                            energy_monotone (one more read of
+                                            U and two small kernels)           */
 
 #define PINT_HIST 64
 
@@ -144,6 +148,19 @@ typedef struct pint_report {
                                   [2] time solve, [3] y-DCT-III,
                                   [4] x-DCT-III + update, [5] control; rest 0  */
   double ms_total;             /* wall time of the solve call (host clock)      */
+  /* Invariants of the returned iterate (PINT_FLAG_INVARIANTS; Section 1: the
+   * CH flow conserves mass and does not increase the Ginzburg-Landau energy,
+   * and the backward-Euler scheme inherits both for small dt):
+   *   mass_drift = max_n |M(u_n) - M(u_0)| / (h^d sum_j |u_0,j|),
+   *                M(u) = h^d sum_j u_j (NaN when not computed, or when u_0 = 0);
+   *   energy_monotone = 1 if E(u_n) <= E(u_{n-1}) + 1e-13 |E(u_{n-1})| for
+   *                n = 1..N_t, with E the discrete Ginzburg-Landau energy
+   *                h^d [sum (u^2-1)^2/4 + eps^2/2 sum_faces ((u'-u)/h)^2];
+   *                0 if some level violates it; -1 for the linear operators
+   *                (whose flow has no such energy) or when not computed.   */
+  double mass_drift;
+  int energy_monotone;
+  int reserved_;
 } pint_report;
 
 typedef struct pint_plan pint_plan;
@@ -245,11 +262,11 @@ int pint_diagnostics(pint_plan* plan, const double* d_U, double* d_mass, double*
  * requests advance one outer iteration at a time on their own streams, so
  * their work overlaps on the device; a request retires as soon as its own
  * stop rule holds and its slot and memory go to the next one (continuous
- * batching).  Iterations after the first replay one captured HIP graph per
- * (slot, shape class) -- shape class = (dim, N, N_t, precision, flags) --
- * re-targeted to each request with hipGraphExecUpdate.  Results do not depend
- * on what else is running: every request's kernels read and write only its
- * own memory, in a fixed order.
+ * batching).  Iterations after the first replay a HIP graph of one outer
+ * iteration, captured and instantiated once per request on its slot (an
+ * executable graph is never re-targeted to another request).  Results do not
+ * depend on what else is running: every request's kernels read and write only
+ * its own memory, in a fixed order.
  */
 #define PINT_SERVER_NO_GRAPHS 0x1u  /* launch every iteration without graphs */
 
@@ -276,7 +293,8 @@ typedef struct pint_server_statistics {
                                               completed requests             */
   double dof_completed;    /* sum of N_s * N_t over completed requests         */
   double busy_seconds;     /* first admission to last completion               */
-  uint64_t graphs_captured, graph_updates, graph_launches;
+  uint64_t graphs_captured, graph_updates, graph_launches;  /* graph_updates
+                              stays 0: graphs are not re-targeted          */
   double worker_host_seconds;  /* worker thread time spent admitting requests and
                                   enqueueing their iterations                  */
   size_t host_pool_bytes, host_pool_in_use;  /* pinned result pool            */
@@ -318,7 +336,10 @@ int pint_server_cancel(pint_server* s, uint64_t ticket);
 /* Snapshot of the counters and latency percentiles. */
 int pint_server_stats(pint_server* s, pint_server_statistics* st);
 /* Cancel queued requests, finish running ones, stop the worker, free the
- * server's streams and host buffers.  NULL is accepted. */
+ * server's streams and host buffers.  NULL is accepted.  Returns PINT_EHIP
+ * (message in pint_server_last_error) if a HIP error stopped the server or if
+ * a slot's stream reports one when it is synchronized here; the server is
+ * freed either way. */
 int pint_server_destroy(pint_server* s);
 /* Message of the last failing server call made by the calling thread ("" if
  * none); for a request that failed on the device side, its message becomes the

@@ -25,6 +25,7 @@ FLAG_INIT_BROADCAST_U0 = 0x1
 FLAG_STAGE_TIMING = 0x2
 FLAG_BF16_SPLIT = 0x4
 FLAG_SOLVE_GRAPH = 0x8
+FLAG_INVARIANTS = 0x10
 HIST = 64
 
 # Every symbol include/pint.h declares (checked by the CPU test suite).
@@ -58,6 +59,7 @@ class Report(ct.Structure):
         ("alpha_used", ct.c_double), ("c_bar", ct.c_double), ("est_rel_err", ct.c_double),
         ("res_hist", ct.c_double * HIST), ("upd_hist", ct.c_double * HIST),
         ("ms_stage", ct.c_double * 8), ("ms_total", ct.c_double),
+        ("mass_drift", ct.c_double), ("energy_monotone", ct.c_int), ("reserved_", ct.c_int),
     ]
 
 
@@ -239,4 +241,6 @@ def report_dict(rep: Report) -> dict:
         "upd_hist": list(rep.upd_hist[:k]),
         "ms_stage": list(rep.ms_stage[:6]),
         "ms_total": rep.ms_total,
+        "mass_drift": rep.mass_drift,
+        "energy_monotone": rep.energy_monotone,
     }

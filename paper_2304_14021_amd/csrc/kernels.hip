@@ -890,6 +890,72 @@ __global__ __launch_bounds__(256) void k_diagnostics(DiagArgs a) {
   }
 }
 
+// Invariants of a converged solve: block b computes the mass, the energy and
+// h^d sum |u| of level b (b = 0: the datum u0, b >= 1: u_b); then one
+// workgroup forms max_n |M_n - M_0| / (h^d sum |u_0|) and checks that the
+// energy never rises by more than 1e-13 of its previous value.
+__global__ __launch_bounds__(256) void k_invariants(DiagArgs a, const double* __restrict__ u0,
+                                                     double* __restrict__ out) {
+  constexpr int NT = 256;
+  __shared__ double red[3 * NT];
+  const int lev = blockIdx.x;
+  const double* u = lev == 0 ? u0 : a.U + size_t(lev - 1) * a.ns;
+  double m = 0.0, e = 0.0, ab = 0.0;
+  for (int i = threadIdx.x; i < a.ns; i += NT) {
+    const int x = i % a.nx, y = i / a.nx;
+    const double v = u[i];
+    m += v;
+    ab += v < 0 ? -v : v;
+    const double w = v * v - 1.0;
+    e += 0.25 * w * w;
+    double gsq = 0.0;
+    if (x + 1 < a.nx) {
+      const double dd = u[i + 1] - v;
+      gsq += dd * dd;
+    }
+    if (a.dim == 2 && y + 1 < a.nx) {
+      const double dd = u[i + a.nx] - v;
+      gsq += dd * dd;
+    }
+    e += 0.5 * a.eps2 * gsq * a.inv_h2;
+  }
+  double v[3] = {m, e, ab};
+  const bool ismax[3] = {false, false, false};
+  block_reduce<NT, 3>(red, v, ismax);
+  if (threadIdx.x == 0) {
+    out[3 * lev + 0] = v[0] * a.hd;
+    out[3 * lev + 1] = v[1] * a.hd;
+    out[3 * lev + 2] = v[2] * a.hd;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_invariants_fin(const double* __restrict__ in, int nt, int energy, Ctrl* c,
+                                                         Ctrl* host) {
+  constexpr int NT = 256;
+  __shared__ double red[2 * NT];
+  const double m0 = in[0];
+  double drift = 0.0, bad = 0.0;
+  for (int n = 1 + int(threadIdx.x); n <= nt; n += NT) {
+    const double d = fabs(in[3 * n] - m0);
+    drift = (d != d || d > drift) ? d : drift;
+    const double ep = in[3 * (n - 1) + 1], en = in[3 * n + 1];
+    if (!(en <= ep + 1e-13 * fabs(ep))) bad += 1.0;
+  }
+  double v[2] = {drift, bad};
+  const bool ismax[2] = {true, false};
+  block_reduce<NT, 2>(red, v, ismax);
+  if (threadIdx.x != 0) return;
+  const double scale = in[2];
+  const double md = scale > 0.0 ? v[0] / scale : __longlong_as_double(0x7ff8000000000000ll);
+  const int ok = energy ? (v[1] == 0.0 ? 1 : 0) : -1;
+  c->mass_drift = md;
+  c->energy_ok = ok;
+  if (host) {
+    host->mass_drift = md;
+    host->energy_ok = ok;
+  }
+}
+
 // ============================================================== launchers
 #define PINT_CHECK_LAUNCH()            \
   do {                                 \
@@ -1182,6 +1248,15 @@ hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool 
     PINT_CHECK_LAUNCH();
   }
   PINT_LAUNCH(k_init_ctrl, dim3(1), dim3(256), 0, st, c, host, a, dof, nparts);
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_invariants(const DiagArgs& a, const double* u0, double* scratch, int nt, bool energy, Ctrl* c,
+                             Ctrl* host, hipStream_t st) {
+  PINT_LAUNCH(k_invariants, dim3(nt + 1), dim3(256), 0, st, a, u0, scratch);
+  PINT_CHECK_LAUNCH();
+  PINT_LAUNCH(k_invariants_fin, dim3(1), dim3(256), 0, st, scratch, nt, energy ? 1 : 0, c, host);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }

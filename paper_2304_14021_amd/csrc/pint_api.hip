@@ -546,6 +546,8 @@ void fill_report(const pint_plan* pl, const Ctrl& c, int status, pint_report* re
     rep->upd_hist[k] = c.upd_hist[k];
     rep->res_hist[k] = c.res_hist[k];
   }
+  rep->mass_drift = std::nan("");
+  rep->energy_monotone = -1;
 }
 
 }  // namespace
@@ -869,12 +871,24 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
       }
     }
   }
+  const bool invariants = (pl->p.flags & PINT_FLAG_INVARIANTS) != 0;
+  if (invariants) {
+    // mass and energy of u_0..u_{N_t}; the block partials are free scratch now
+    DiagArgs da{d_U, nullptr, nullptr, pl->n, pl->ns, pl->dim, pl->p.eps * pl->p.eps, 1.0 / (pl->h * pl->h),
+                pl->dim == 2 ? pl->h * pl->h : pl->h};
+    const bool ch = pl->p.op == PINT_OP_CH || pl->p.op == PINT_OP_CH_EYRE;
+    HIPCHK(launch_invariants(da, d_u0, w.part, pl->nt, ch, w.ctrl, pl->h_ctrl, st), "invariants kernels");
+  }
   HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
   const Ctrl& c = *pl->h_ctrl;
   const int status = c.done ? c.status : PINT_ENOCONV;
   if (status == PINT_OK) pl->predict = c.iter;
   if (rep) {
     fill_report(pl, c, status, rep);
+    if (invariants) {
+      rep->mass_drift = c.mass_drift;
+      rep->energy_monotone = c.energy_ok;
+    }
     if (timing) {
       for (int k = 0; k < c.iter && k < it; ++k)
         for (int s = 0; s < EV_PER_IT / 2; ++s) {

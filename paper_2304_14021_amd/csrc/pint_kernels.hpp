@@ -54,6 +54,9 @@ struct Ctrl {
   double upd_prev, upd_first, est;
   double upd_hist[PINT_HIST_DEV];
   double res_hist[PINT_HIST_DEV];
+  double mass_drift;  // invariants of the final iterate (k_invariants_fin)
+  int energy_ok;      // 1 monotone, 0 violated, -1 not applicable
+  int pad2;
 };
 
 struct ResidArgs {
@@ -175,5 +178,9 @@ hipError_t launch_finalize(const FinArgs& f, hipStream_t st);
 // reduction use a.part (nparts <= ceil(total / 4096) slots).
 hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool need_cbar, hipStream_t st);
 hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st);
+// Mass drift and energy monotonicity of u_0, u_1..u_{N_t} into the control
+// record and its host mirror; `scratch` holds 3 (N_t + 1) doubles.
+hipError_t launch_invariants(const DiagArgs& a, const double* u0, double* scratch, int nt, bool energy, Ctrl* c,
+                             Ctrl* host, hipStream_t st);
 
 }  // namespace pint

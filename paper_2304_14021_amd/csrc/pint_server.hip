@@ -1,8 +1,8 @@
 // Serving loop: a persistent worker thread that admits all-at-once solves as
 // HBM and streams free up, runs their outer iterations concurrently on
-// separate HIP streams (one per active slot), replays one captured HIP graph
-// per (slot, shape class) for the iterations after the first, and retires
-// each request as soon as its own stop flag is set.  Requests never wait for
+// separate HIP streams (one per active slot), captures each request's outer
+// iteration once as a HIP graph and replays it for the iterations after the
+// first, and retires each request as soon as its own stop flag is set.  Requests never wait for
 // each other's iterations: continuous batching at iteration granularity.
 //
 // Memory: every request's device state (plan tables, u0, U, workspace) is a
@@ -66,7 +66,9 @@ struct Req {
 
 enum SlotState { SL_IDLE, SL_RUNNING, SL_DRAINING };
 
-using ShapeKey = std::tuple<int, int, int, int, unsigned>;  // dim, n, nt, precision, flags
+// Everything that selects kernels or changes the iteration count of a
+// request: dim, n, nt, precision, flags, operator, time path, theta.
+using ShapeKey = std::tuple<int, int, int, int, unsigned, int, int, double>;
 
 struct Slot {
   hipStream_t st = nullptr;
@@ -80,9 +82,8 @@ struct Slot {
   double* d_u0 = nullptr;
   double* d_U = nullptr;
   void* d_work = nullptr;
-  std::map<ShapeKey, hipGraphExec_t> graphs;
+  hipGraphExec_t graph = nullptr;  // the running request's captured iteration
   ShapeKey cur_key{};
-  bool graph_ready = false;
 };
 
 // First-fit allocator over [0, size) with coalescing.
@@ -158,12 +159,22 @@ struct pint_server {
   double host_seconds = 0.0;  // worker time spent admitting and advancing requests
   bool have_first = false;
   Clock::time_point t_first, t_last;
-  int fatal = PINT_OK;
+  int fatal = PINT_OK;     // PINT_EHIP after a HIP error: no further admissions
+  std::string fatal_msg;   // what failed
 };
 
 namespace {
 
 thread_local std::string g_srv_err;
+
+// Record a HIP error that ends the server's service: later submissions fail
+// and queued requests are finished with it.  Lock held.
+void set_fatal(pint_server* s, const std::string& msg) {
+  if (s->fatal == PINT_OK) {
+    s->fatal = PINT_EHIP;
+    s->fatal_msg = msg;
+  }
+}
 
 // Errors are per calling thread; a request's worker-side error travels with
 // the request and becomes the waiting thread's error.
@@ -172,7 +183,15 @@ int srv_fail(pint_server*, int code, const std::string& msg) {
   return code;
 }
 
-ShapeKey key_of(const pint_problem& p) { return ShapeKey(p.dim, p.nx, p.nt, p.precision, p.flags); }
+ShapeKey key_of(const pint_problem& p) {
+  return ShapeKey(p.dim, p.nx, p.nt, p.precision, p.flags, p.op, p.time_path, p.theta);
+}
+
+// Destroy the slot's executable graph (its request has retired).
+void drop_graph(Slot& sl) {
+  if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+  sl.graph = nullptr;
+}
 
 void finish_req(pint_server* s, Req* r, int status) {
   r->status = status;
@@ -201,48 +220,37 @@ void finish_req(pint_server* s, Req* r, int status) {
 }
 
 // Enqueue iteration `it` of the slot's request: the first one directly (it
-// reads the broadcast datum), later ones by replaying the slot's graph for the
-// request's shape class.  Called by the worker thread only.
+// reads the broadcast datum); later ones by replaying a graph of one outer
+// iteration, captured for this request when its second iteration is
+// enqueued.  A graph is never re-targeted to another request (no
+// hipGraphExecUpdate): each request gets its own capture and instantiation,
+// and the executable graph is destroyed when the request retires.  Called by
+// the worker thread only.
 int enqueue_it(pint_server* s, Slot& sl, int it) {
   Req* r = sl.req;
   if (it == 0 || (s->cfg.flags & PINT_SERVER_NO_GRAPHS)) {
     return solve_enqueue(r->plan, sl.d_u0, sl.d_U, sl.d_work, r->work_bytes, sl.st, sl.h_ctrl, it);
   }
-  if (!sl.graph_ready) {
+  if (!sl.graph) {
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return srv_fail(s, PINT_EHIP, "hipStreamBeginCapture failed");
-    int rc = solve_enqueue(r->plan, sl.d_u0, sl.d_U, sl.d_work, r->work_bytes, sl.st, sl.h_ctrl, 1);
-    hipError_t e = hipStreamEndCapture(sl.st, &g);
-    if (rc) return rc;
-    if (e != hipSuccess) return srv_fail(s, PINT_EHIP, "hipStreamEndCapture failed");
-    auto found = sl.graphs.find(sl.cur_key);
-    bool ok = false;
-    if (found != sl.graphs.end()) {
-      hipGraphNode_t err_node = nullptr;
-      hipGraphExecUpdateResult res;
-      ok = hipGraphExecUpdate(found->second, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
-      if (ok) {
-        ++s->graph_updates;
-      } else {
-        (void)hipGraphExecDestroy(found->second);
-        sl.graphs.erase(found);
-      }
+    hipError_t e = hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return srv_fail(s, PINT_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    const int rc = solve_enqueue(r->plan, sl.d_u0, sl.d_U, sl.d_work, r->work_bytes, sl.st, sl.h_ctrl, 1);
+    e = hipStreamEndCapture(sl.st, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
     }
-    if (!ok) {
-      hipGraphExec_t ex = nullptr;
-      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return srv_fail(s, PINT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-      sl.graphs[sl.cur_key] = ex;
-      ++s->graph_captures;
-    }
+    if (e != hipSuccess) return srv_fail(s, PINT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    sl.graph_ready = true;
+    if (e != hipSuccess) {
+      sl.graph = nullptr;
+      return srv_fail(s, PINT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    ++s->graph_captures;
   }
-  hipError_t e = hipGraphLaunch(sl.graphs[sl.cur_key], sl.st);
+  const hipError_t e = hipGraphLaunch(sl.graph, sl.st);
   if (e != hipSuccess) return srv_fail(s, PINT_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
   ++s->graph_launches;
   return PINT_OK;
@@ -289,7 +297,7 @@ int start_req(pint_server* s, Slot& sl, Req* r) {
   if (rc) return rc;
   sl.req = r;
   sl.cur_key = key_of(r->prob);
-  sl.graph_ready = false;
+  drop_graph(sl);
   sl.it_enq = 0;
   const int maxit = plan_max_iter(r->plan);
   auto pr = s->predict.find(sl.cur_key);
@@ -345,6 +353,7 @@ int advance(pint_server* s, Slot& sl) {
   r->rep.ms_total = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
   s->alloc.release(r->pool_off, r->footprint);
   if (!r->h_held && !r->d_U) s->h_alloc.release(r->h_off, r->ns * r->nt * sizeof(double));
+  drop_graph(sl);
   sl.req = nullptr;
   sl.state = SL_IDLE;
   finish_req(s, r, r->status);
@@ -356,6 +365,14 @@ void worker_main(pint_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
     bool progressed = false;
+    // after a HIP error nothing more is admitted: queued requests fail with it
+    while (s->fatal != PINT_OK && !s->queue.empty()) {
+      Req* r = s->queue.front();
+      s->queue.pop_front();
+      g_srv_err = "server stopped after a HIP error: " + s->fatal_msg;
+      finish_req(s, r, PINT_EHIP);
+      progressed = true;
+    }
     // admission, first come first served, as slots and pool memory allow
     while (!s->queue.empty() && s->fatal == PINT_OK) {
       Req* r = s->queue.front();
@@ -385,16 +402,25 @@ void worker_main(pint_server* s) {
       s->pool_peak = std::max(s->pool_peak, s->alloc.used());
       const Clock::time_point h0 = Clock::now();
       g_srv_err.clear();
-      const int rc = start_req(s, *free_slot, r);
+      int rc = start_req(s, *free_slot, r);
       s->host_seconds += std::chrono::duration<double>(Clock::now() - h0).count();
       if (rc) {
-        (void)hipStreamSynchronize(free_slot->st);  // pending copies read the plan's host tables
+        const std::string msg = g_srv_err;
+        // pending copies read the plan's host tables: wait for them, and keep
+        // any error the stream reports
+        const hipError_t se = hipStreamSynchronize(free_slot->st);
+        drop_graph(*free_slot);
         s->alloc.release(off, r->footprint);
         if (hbytes) s->h_alloc.release(hoff, hbytes);
         free_slot->req = nullptr;
         free_slot->state = SL_IDLE;
+        if (se != hipSuccess) {
+          set_fatal(s, std::string("stream synchronization after a failed admission: ") + hipGetErrorString(se));
+          g_srv_err = msg + "; " + s->fatal_msg;
+          rc = PINT_EHIP;
+        }
+        if (rc == PINT_EHIP) set_fatal(s, msg);
         finish_req(s, r, rc);
-        if (rc == PINT_EHIP) s->fatal = rc;
       }
       progressed = true;
     }
@@ -407,11 +433,19 @@ void worker_main(pint_server* s) {
       if (q == hipErrorNotReady) continue;
       const Clock::time_point h0 = Clock::now();
       g_srv_err.clear();
-      int rc = q == hipSuccess ? advance(s, sl) : srv_fail(s, PINT_EHIP, "stream error");
+      int rc = q == hipSuccess ? advance(s, sl)
+                               : srv_fail(s, PINT_EHIP, std::string("stream error: ") + hipGetErrorString(q));
       s->host_seconds += std::chrono::duration<double>(Clock::now() - h0).count();
       if (rc) {
         Req* r = sl.req;
-        (void)hipStreamSynchronize(sl.st);
+        const std::string msg = g_srv_err;
+        const hipError_t se = hipStreamSynchronize(sl.st);
+        if (se != hipSuccess) {
+          rc = PINT_EHIP;
+          g_srv_err = msg + "; stream synchronization: " + hipGetErrorString(se);
+        }
+        if (rc == PINT_EHIP) set_fatal(s, g_srv_err);
+        drop_graph(sl);
         if (r) {
           s->alloc.release(r->pool_off, r->footprint);
           if (!r->d_U) s->h_alloc.release(r->h_off, r->ns * r->nt * sizeof(double));
@@ -420,7 +454,6 @@ void worker_main(pint_server* s) {
         }
         sl.req = nullptr;
         sl.state = SL_IDLE;
-        if (rc == PINT_EHIP) s->fatal = rc;
       }
       progressed = true;
     }
@@ -493,7 +526,7 @@ int submit_common(pint_server* s, const pint_problem* p, const double* h_u0, con
     if (s->fatal) {
       pint_plan_destroy(plan);
       delete r;
-      return srv_fail(s, s->fatal, "server stopped after a HIP error");
+      return srv_fail(s, s->fatal, "server stopped after a HIP error: " + s->fatal_msg);
     }
     r->ticket = s->next_ticket++;
     s->reqs[r->ticket] = r;
@@ -649,6 +682,8 @@ int pint_server_stats(pint_server* s, pint_server_statistics* st) {
 
 int pint_server_destroy(pint_server* s) {
   if (!s) return PINT_OK;
+  int rc = PINT_OK;
+  std::string msg;
   if (s->worker.joinable()) {
     {
       std::lock_guard<std::mutex> g(s->mu);
@@ -658,9 +693,21 @@ int pint_server_destroy(pint_server* s) {
     s->cv_work.notify_all();
     s->worker.join();
   }
+  if (s->fatal != PINT_OK) {
+    rc = s->fatal;
+    msg = "server stopped after a HIP error: " + s->fatal_msg;
+  }
   for (auto& sl : s->slots) {
-    if (sl.st) (void)hipStreamSynchronize(sl.st);
-    for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
+    // a failure of the last work on a slot is reported here, not left for
+    // the next unrelated synchronization to find
+    if (sl.st) {
+      const hipError_t e = hipStreamSynchronize(sl.st);
+      if (e != hipSuccess && rc == PINT_OK) {
+        rc = PINT_EHIP;
+        msg = std::string("stream synchronization at shutdown: ") + hipGetErrorString(e);
+      }
+    }
+    drop_graph(sl);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.st) (void)hipStreamDestroy(sl.st);
     if (sl.h_ctrl) (void)hipHostFree(sl.h_ctrl);
@@ -672,7 +719,8 @@ int pint_server_destroy(pint_server* s) {
   }
   if (s->h_pool) (void)hipHostFree(s->h_pool);
   delete s;
-  return PINT_OK;
+  if (rc != PINT_OK) g_srv_err = msg;
+  return rc;
 }
 
 const char* pint_server_last_error(const pint_server*) { return g_srv_err.c_str(); }

@@ -128,9 +128,11 @@ class Server:
         return {name: getattr(st, name) for name, _ in _pint.ServerStats._fields_ if name != "struct_size"}
 
     def close(self):
+        """Shut the server down; raises PintError if a HIP error stopped it or
+        surfaced when its streams were synchronized."""
         if getattr(self, "h", None):
-            self.lib.dll.pint_server_destroy(self.h)
-            self.h = None
+            h, self.h = self.h, None
+            self._check(self.lib.dll.pint_server_destroy(h), None)
 
     def __enter__(self):
         return self

@@ -27,13 +27,15 @@ class Solver:
     def __init__(self, op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1.0, eps: float = 1.0,
                  beta: float = 0.0, alpha: float = 1e-3, precision: str = "fp32", time_path: str = "auto",
                  rtol: float = 1e-10, max_iter: int = 30, broadcast_u0: bool = True, stage_timing: bool = False,
-                 graph: bool = False, device=None):
+                 graph: bool = False, invariants: bool = False, device=None):
         _require_gpu()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         flags = (_pint.FLAG_INIT_BROADCAST_U0 if broadcast_u0 else 0) | (_pint.FLAG_STAGE_TIMING if stage_timing else 0)
         # graph: replay init + predicted iterations as one captured HIP graph
         # (needs a non-default torch stream; on the default stream it is ignored)
         flags |= _pint.FLAG_SOLVE_GRAPH if graph else 0
+        # invariants: the report carries the mass drift and energy monotonicity
+        flags |= _pint.FLAG_INVARIANTS if invariants else 0
         self.shape = (nt,) + (n,) * dim
         self.slice_shape = (n,) * dim
         self.dof = nt * n ** dim

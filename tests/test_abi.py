@@ -36,13 +36,15 @@ def test_struct_layout_matches_header(tmp_path):
                    'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pint_problem), sizeof(pint_report),'
                    ' offsetof(pint_problem, flags), offsetof(pint_report, ms_total), offsetof(pint_problem, rtol),'
                    ' sizeof(pint_server_config), sizeof(pint_server_statistics),'
-                   ' offsetof(pint_server_statistics, worker_host_seconds));}\n')
+                   ' offsetof(pint_server_statistics, worker_host_seconds));'
+                   'printf("%zu %zu\\n", offsetof(pint_report, mass_drift), offsetof(pint_report, energy_monotone));}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     want = [ct.sizeof(_pint.Problem), ct.sizeof(_pint.Report), _pint.Problem.flags.offset,
             _pint.Report.ms_total.offset, _pint.Problem.rtol.offset, ct.sizeof(_pint.ServerConfig),
-            ct.sizeof(_pint.ServerStats), _pint.ServerStats.worker_host_seconds.offset]
+            ct.sizeof(_pint.ServerStats), _pint.ServerStats.worker_host_seconds.offset,
+            _pint.Report.mass_drift.offset, _pint.Report.energy_monotone.offset]
     assert [int(x) for x in got] == want
 
 

@@ -75,11 +75,12 @@ def test_served_against_oracle():
 
 
 @pytest.mark.skip(reason="a GPU memory fault was observed in this test's run (illegal address at the "
-                         "standalone solve after the served requests); its cause is not shown yet, so the "
-                         "case stays off the GPU until it is")
+                         "standalone solve after the served requests) while executable graphs were "
+                         "re-targeted with hipGraphExecUpdate; its cause was not shown, that path has been "
+                         "removed from the server, and this case stays off the GPU")
 def test_graph_reuse_within_a_shape_class():
     # one slot, several requests of one shape class with different
-    # coefficients: one capture, then executable-graph updates
+    # coefficients: one capture, then executable-graph updates (path removed)
     base = Problem(op="linear_ch", dim=2, n=32, nt=32, dt=1e-5, eps=0.05, beta=0.3, alpha=1e-3)
     ps = [dataclasses.replace(base, eps=e) for e in (0.03, 0.05, 0.07)]
     rng = np.random.default_rng(3)
@@ -254,3 +255,29 @@ def test_served_fp64_small_alpha_two_steps():
         say(f"  request {i} {r.problem.op} n{r.problem.n} nt{r.problem.nt} fp64 alpha 1e-6: "
             f"it {rep['iterations']} err {err:.2e}")
         assert rep["status"] == 0 and rep["iterations"] == 2 and err <= 1e-10
+
+
+def test_served_dense_and_fft_requests_of_one_shape():
+    # requests that differ only in their time path (dense FP32 MFMA vs FFT) and
+    # coefficients, on two slots: each one is captured on its own, and every
+    # result equals its standalone solve bit for bit
+    shape = dict(op="linear_ch", dim=2, n=32, nt=32, dt=1e-5, beta=0.3, alpha=1e-3)
+    combos = [("dense", 0.03), ("fft", 0.05), ("dense", 0.07), ("fft", 0.04)]
+    rng = np.random.default_rng(23)
+    u0s = [rng.uniform(-0.05, 0.05, (32, 32)) for _ in combos]
+    structs = [_pint.make_problem(shape["op"], 2, 32, 32, 1e-5, eps=e, beta=0.3, alpha=1e-3, precision="mixed",
+                                  time_path=tp) for tp, e in combos]
+    say(f"served dense/fft mix: {combos}")
+    with Server(1 << 28, max_active=2, device=dev()) as srv:
+        ts = [srv.submit(q, u) for q, u in zip(structs, u0s)]
+        res = [srv.wait(t) for t in ts]
+        st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(combos) and st["graph_updates"] == 0
+    assert st["graphs_captured"] == len(combos)
+    for (tp, e), u0, (U, rep) in zip(combos, u0s, res):
+        s = Solver(shape["op"], 2, 32, 32, 1e-5, eps=e, beta=0.3, alpha=1e-3, precision="mixed", time_path=tp,
+                   device=dev())
+        Ud, rrep = s.solve(to_dev(u0))
+        assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
+        assert np.array_equal(U, host(Ud)), f"{tp} eps {e}"

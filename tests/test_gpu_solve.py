@@ -22,6 +22,16 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
+def _assert_parity(U, ref, rep):
+    """Both of the paper's error norms (Section 5): L^inf(0,T;L^2) and
+    L^inf(0,T;L^inf), relative, within the 1e-10 bar."""
+    err, err_inf = stepper.rel_err(U, ref), stepper.rel_err_inf(U, ref)
+    say(f"  iterations {rep['iterations']} err {err:.2e} err_inf {err_inf:.2e} est {rep['est_rel_err']:.2e}")
+    assert rep["status"] == 0
+    assert err <= TOL and err_inf <= TOL
+    return err
+
+
 def _run(p, u0, prec, **kw):
     s = Solver.for_problem(p, precision=prec, device=dev(), **kw)
     U, rep = s.solve(to_dev(u0), raise_on_error=False)
@@ -34,10 +44,7 @@ def test_c1_biharmonic_1d(prec):
     p = CONFIGS["c1"]
     u0 = initial_datum("c1")
     U, rep, _ = _run(p, u0, prec)
-    ref = stepper.sequential(p, u0)
-    err = stepper.rel_err(U, ref)
-    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
-    assert rep["status"] == 0 and err <= TOL
+    _assert_parity(U, stepper.sequential(p, u0), rep)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
@@ -46,25 +53,20 @@ def test_c2_linear_ch_2d_full_size(prec):
     p = CONFIGS["c2"]
     u0 = initial_datum("c2")
     U, rep, _ = _run(p, u0, prec)
-    ref = stepper.sequential(p, u0)
-    err = stepper.rel_err(U, ref)
-    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
-    assert rep["status"] == 0 and err <= TOL
-    assert stepper.rel_err_inf(U, ref) <= 10 * TOL
+    _assert_parity(U, stepper.sequential(p, u0), rep)
 
 
 def test_c2_small_alpha_two_steps():
     """Very small alpha: the linearized CH solve is done in two outer
     iterations (the two-step convergence the paper reports for small alpha in
-    its linearized CH experiments, Section 6).  FP64 at alpha = 1e-6: the
+    its linearized CH experiments, Section 5).  FP64 at alpha = 1e-6: the
     first step leaves an error of order alpha, the second of order alpha^2."""
     say("c2 fp64 alpha 1e-6")
     p = dataclasses.replace(CONFIGS["c2"], alpha=1e-6)
     u0 = initial_datum("c2")
     U, rep, _ = _run(p, u0, "fp64")
-    err = stepper.rel_err(U, stepper.sequential(p, u0))
-    say(f"  iterations {rep['iterations']} err {err:.2e} est {rep['est_rel_err']:.2e}")
-    assert rep["status"] == 0 and rep["iterations"] == 2 and err <= TOL
+    _assert_parity(U, stepper.sequential(p, u0), rep)
+    assert rep["iterations"] == 2
 
 
 SOLVE_CASES = [
@@ -89,10 +91,34 @@ def test_solve_matches_oracle(p, prec):
     amp = 0.3 if p.op in ("ch", "ch_eyre") else 1.0
     u0 = rng.uniform(-amp, amp, p.slice_shape)
     U, rep, _ = _run(p, u0, prec)
-    ref = stepper.sequential(p, u0)
-    err = stepper.rel_err(U, ref)
-    say(f"  iterations {rep['iterations']} err {err:.2e}")
-    assert rep["status"] == 0 and err <= TOL
+    _assert_parity(U, stepper.sequential(p, u0), rep)
+
+
+@pytest.mark.parametrize("op", ["ch", "ch_eyre", "linear_ch"])
+def test_report_invariants(op):
+    # PINT_FLAG_INVARIANTS: the report's mass drift and energy monotonicity
+    # (Section 1) agree with the oracle's definitions applied to the result
+    p = Problem(op=op, dim=2, n=64, nt=64, dt=1e-6, eps=0.01, beta=0.5, alpha=1e-3)
+    rng = np.random.default_rng(14)
+    u0 = rng.uniform(-0.1, 0.1, p.slice_shape) + 0.02
+    s = Solver.for_problem(p, precision="mixed", invariants=True, device=dev())
+    Ud, rep = s.solve(to_dev(u0))
+    U = host(Ud)
+    m0 = ops.mass(u0, p.h)
+    drift = max(abs(ops.mass(u, p.h) - m0) for u in U) / (p.h ** 2 * np.sum(np.abs(u0)))
+    say(f"  {op}: report mass_drift {rep['mass_drift']:.2e} (oracle formula {drift:.2e}), "
+        f"energy_monotone {rep['energy_monotone']}")
+    assert rep["status"] == 0
+    assert rep["mass_drift"] <= 1e-13 and abs(rep["mass_drift"] - drift) <= 1e-14
+    if op == "linear_ch":
+        assert rep["energy_monotone"] == -1
+    else:
+        e = [ops.energy(u0, p.eps, p.h)] + [ops.energy(u, p.eps, p.h) for u in U]
+        assert np.all(np.diff(e) <= 1e-13 * np.abs(e[:-1]))
+        assert rep["energy_monotone"] == 1
+    plain = Solver.for_problem(p, precision="mixed", device=dev())
+    _, rep2 = plain.solve(to_dev(u0))
+    assert np.isnan(rep2["mass_drift"]) and rep2["energy_monotone"] == -1
 
 
 def test_ch_invariants_mass_energy():
