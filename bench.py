@@ -152,6 +152,9 @@ def golden_deviation(name: str, U) -> dict:
     """Deviation of a GPU result from the stored oracle data of the workload
     (relative to max_n ||u_n^ref||_2; 'rel' <= 1e-10 is the paper's bar)."""
     from tests import _golden
+    if not os.path.exists(os.path.join(_golden.GOLDEN_DIR, f"{name}_samples.json")):
+        log(f"no stored oracle data for {name}: result not checked")
+        return {"rel": None}
     return _golden.compare(U.cpu().numpy() if hasattr(U, "cpu") else U, _golden.load(name))
 
 
@@ -521,7 +524,10 @@ def main():
             variants += [(args.precision, "fft", p.alpha)]
         variants += [("fp32_norefine", "fft", None)]  # the unrefined plateau (not at the 1e-10 bar)
         # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
-        bf16_alpha = 4e-3 if name == "c5" else BF16_ALPHA
+        # at 512^2 x 1024 the alpha part of the contraction, alpha R^{N_t} / (1 - alpha R^{N_t}) with
+        # R^{N_t} ~ exp(T / (4 eps^2)) ~ 85, is 0.09 at alpha = 1e-3 and 0.5 at 4e-3 (which then does not
+        # converge together with the scalar-Jacobian rate); BF16 rounding grows like u_bf16 / alpha
+        bf16_alpha = 1e-3 if name == "c5" else BF16_ALPHA
         variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", bf16_alpha),
                      ("bf16", "dense", bf16_alpha), ("bf16_norefine", "dense", bf16_alpha)]
         for prec, tp, al in variants:

@@ -131,6 +131,23 @@ typedef struct pint_problem {
   double rtol;         /* target relative error (L^inf(L^2)); 0 = 1e-10        */
   int max_iter;        /* cap on outer iterations (<= PINT_HIST); 0 = 30       */
   unsigned flags;      /* PINT_FLAG_*                                          */
+  /* Nonuniform time steps (Section 1, direct diagonalization with variable
+   * steps): NULL for the uniform step dt; else nt positive, pairwise distinct
+   * steps dt_1..dt_nt (host memory, copied by pint_plan_create; dt is then
+   * ignored and T = sum dt_n).  The time-step pencil of the theta-method,
+   * B = diag(1/dt_n)(I - S), C = theta I + (1 - theta) S (S the down-shift),
+   * is no longer alpha-circulant: the plan diagonalizes it directly,
+   * B V = C V D, in FP64 on the GPU (one eigenpair per thread, by forward and
+   * backward substitution in the bidiagonal pencil), and the time solve is
+   * the dense contraction x -> V (D + shift_k)^{-1} V^{-1} C^{-1} x per spatial
+   * mode (FP32 MFMA for FP32_REFINE and MIXED, FP64 for FP64), wrapped in the
+   * same FP64 residual refinement.  alpha is not used.  Operators: the linear
+   * ones (theta 1 or 1/2) and PINT_OP_CH (backward Euler); time path AUTO or
+   * DENSE; precision FP64, FP32_REFINE or MIXED.  N_t >= 32 (the contraction
+   * tile), and the time-step pencil's eigenvector matrix V grows
+   * ill-conditioned as neighbouring steps approach each other: the refinement
+   * then needs more iterations or stops converging (PINT_ENOCONV). */
+  const double* dts;
 } pint_problem;
 
 /* Outcome of one solve (filled by the library when a pointer is passed). */
@@ -247,6 +264,15 @@ int pint_time_solve(pint_plan* plan, void* d_S, double c_bar, void* stream);
  * working-precision DCT and time solve. */
 int pint_precond_apply(pint_plan* plan, const double* d_r, double* d_delta, double c_bar,
                        void* d_work, size_t work_bytes, void* stream);
+
+/* The FP64 eigendecomposition of the time-step pencil of a plan with
+ * nonuniform steps (pint_problem.dts; Section 1): h_V [N_t][N_t] with the
+ * unit-norm right eigenvectors as columns, h_W [N_t][N_t] with the left ones
+ * as rows, scaled so that W C V = I, and h_d [N_t] the eigenvalues
+ * d_j = 1/(theta dt_j), so that B V = C V diag(d).  Host buffers, caller-owned;
+ * the call copies from the plan's device tables and synchronizes the device.
+ * PINT_EINVAL for a plan with uniform steps. */
+int pint_time_eig(pint_plan* plan, double* h_V, double* h_W, double* h_d);
 
 /* Diagnostics of a space-time state: per-level discrete mass h^d sum u and
  * Ginzburg-Landau energy h^d [sum (u^2-1)^2/4 + eps^2/2 sum_faces ((u'-u)/h)^2]

@@ -302,22 +302,24 @@ def time_solve_modal(p, rh: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
 
 
 def time_solve_steps_modal(p, rh: np.ndarray, dts, c_bar: float = 0.0) -> np.ndarray:
-    """The space-time solve with nonuniform backward-Euler steps in the cosine
-    basis: per spatial mode k the dense N_t x N_t system (B + mu_k I) y = x
-    (linear; theta = 1), or (B + ((1 - c_bar) lam_k + eps^2 lam_k^2) I) y = x
-    (CH with the scalar averaged Jacobian), solved by numpy.linalg.solve --
-    no eigendecomposition."""
+    """The space-time solve with nonuniform steps in the cosine basis: per
+    spatial mode k the dense N_t x N_t system (B + mu_k C) y = x of the linear
+    theta-method (B, C from ``step_blocks``; C = I for backward Euler), or
+    (B + ((1 - c_bar) lam_k + eps^2 lam_k^2) I) y = x (backward-Euler CH with
+    the scalar averaged Jacobian), solved by numpy.linalg.solve -- no
+    eigendecomposition."""
     nt = p.nt
     x = rh.reshape(nt, -1)
     lam, mu = spatial_symbols(p)
-    b, _ = step_blocks(dts, 1.0)
-    if p.op in ("biharmonic", "linear_ch"):
+    linear = p.op in ("biharmonic", "linear_ch")
+    b, c = step_blocks(dts, p.theta if linear else 1.0)
+    if linear:
         shift = mu
     elif p.op == "ch":
         shift = (1.0 - c_bar) * lam + p.eps ** 2 * lam * lam
     else:
         raise ValueError(p.op)
-    mats = b[None] + shift[:, None, None] * np.eye(nt)[None]
+    mats = b[None] + shift[:, None, None] * c[None]
     sol = np.linalg.solve(mats, x.T[:, :, None])[:, :, 0]
     return sol.T.reshape(rh.shape)
 

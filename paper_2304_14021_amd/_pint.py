@@ -33,7 +33,7 @@ EXPORTS = (
     "pint_status_string", "pint_last_error", "pint_version",
     "pint_plan_create", "pint_plan_destroy", "pint_plan_last_error", "pint_plan_workspace_size",
     "pint_plan_alpha", "pint_solve", "pint_residual", "pint_dct", "pint_time_solve",
-    "pint_precond_apply", "pint_diagnostics",
+    "pint_precond_apply", "pint_diagnostics", "pint_time_eig",
     "pint_server_create", "pint_server_submit", "pint_server_submit_device", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
     "pint_server_destroy", "pint_server_last_error",
 )
@@ -49,6 +49,7 @@ class Problem(ct.Structure):
         ("alpha", ct.c_double),
         ("precision", ct.c_int), ("time_path", ct.c_int),
         ("rtol", ct.c_double), ("max_iter", ct.c_int), ("flags", ct.c_uint),
+        ("dts", ct.POINTER(ct.c_double)),
     ]
 
 
@@ -118,6 +119,7 @@ class Lib:
         d.pint_time_solve.argtypes = [vp, vp, dbl, vp]
         d.pint_precond_apply.argtypes = [vp, vp, vp, dbl, vp, sz, vp]
         d.pint_diagnostics.argtypes = [vp, vp, vp, vp, vp]
+        d.pint_time_eig.argtypes = [vp, vp, vp, vp]
         d.pint_server_create.argtypes = [ct.POINTER(ServerConfig), ct.POINTER(vp)]
         d.pint_server_submit.argtypes = [vp, ct.POINTER(Problem), vp, ct.POINTER(ct.c_uint64)]
         d.pint_server_submit_device.argtypes = [vp, ct.POINTER(Problem), vp, vp, ct.POINTER(ct.c_uint64)]
@@ -152,7 +154,10 @@ def lib() -> Lib:
 
 def make_problem(op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1.0, eps: float = 1.0,
                  beta: float = 0.0, alpha: float = 1e-3, precision: str = "fp32", time_path: str = "auto",
-                 rtol: float = 1e-10, max_iter: int = 30, flags: int = 0, length: float = 1.0) -> Problem:
+                 rtol: float = 1e-10, max_iter: int = 30, flags: int = 0, length: float = 1.0,
+                 dts=None) -> Problem:
+    """A pint_problem struct.  dts: optional nonuniform steps (nt values); the
+    array is kept referenced by the struct (``p._dts``) until it is dropped."""
     p = Problem()
     p.struct_size = ct.sizeof(Problem)
     p.op = OPS[op]
@@ -173,6 +178,13 @@ def make_problem(op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1
     p.rtol = rtol
     p.max_iter = max_iter
     p.flags = flags
+    if dts is not None:
+        import numpy as np
+        arr = np.ascontiguousarray(dts, dtype=np.float64)
+        if arr.shape != (nt,):
+            raise ValueError(f"dts must hold nt = {nt} steps")
+        p._dts = arr
+        p.dts = arr.ctypes.data_as(ct.POINTER(ct.c_double))
     return p
 
 
@@ -224,6 +236,14 @@ class Plan:
     def precond_raw(self, r_ptr, d_ptr, c_bar, work_ptr, work_bytes, stream=0):
         self.lib.check(self.lib.dll.pint_precond_apply(self.h, r_ptr, d_ptr, c_bar, work_ptr, work_bytes, stream),
                        self.h)
+
+    def time_eig(self):
+        """(V, W, d) of the plan's FP64 time-step eigendecomposition (host arrays)."""
+        import numpy as np
+        nt = self.problem.nt
+        V, W, d = np.empty((nt, nt)), np.empty((nt, nt)), np.empty(nt)
+        self.lib.check(self.lib.dll.pint_time_eig(self.h, V.ctypes.data, W.ctypes.data, d.ctypes.data), self.h)
+        return V, W, d
 
     def diagnostics_raw(self, U_ptr, mass_ptr, energy_ptr, stream=0):
         self.lib.check(self.lib.dll.pint_diagnostics(self.h, U_ptr, mass_ptr, energy_ptr, stream), self.h)

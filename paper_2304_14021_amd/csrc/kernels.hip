@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (a.done && *a.done) return;
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
-  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
+  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = zrows(N) * ES * int(sizeof(cx<T>));
   constexpr int R0 = VB > ZB ? VB : ZB;
   constexpr int NV = DIM == 2 ? 1 : RB;
   constexpr int RED = NT * NV * 8;  // reduction scratch, reuses the G region
@@ -96,8 +96,21 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   }
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
-  const int lev = DIM == 2 ? b / NBL : b * RB;
-  const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
+  int lev = DIM == 2 ? b / NBL : b * RB;
+  int strip = DIM == 2 ? b - (b / NBL) * NBL : 0;
+  if constexpr (DIM == 2 && NBL % 8 == 0) {
+    if (a.xcd_order) {
+      // Workgroups are dealt to the 8 XCDs round-robin.  XCD x takes the strips
+      // [x G, (x+1) G) (G = NBL / 8) of every level, level after level, so the
+      // halo rows shared by neighbouring strips and the rows of u_n that the
+      // next level's blocks read again as u_{n-1} meet in one L2.
+      constexpr int G = NBL / 8;
+      const int x = b & 7, j = b >> 3;
+      lev = j / G;
+      strip = x * G + (j - (j / G) * G);
+    }
+  }
+  const int y0 = strip * RB;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
   const bool bc = a.bcast != 0;
   const double th = a.theta, omth = 1.0 - a.theta;
@@ -197,7 +210,8 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     const RT gv = G[gc * N + x];
     RT lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - RT(2) * gv;
     if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - RT(2) * gv;
-    const RT r = -d[i] * RT(a.inv_dt) + lap * RT(a.inv_h2);
+    const int nl = DIM == 2 ? lev : lev + rr;
+    const RT r = -d[i] * RT(a.inv_dts ? a.inv_dts[nl] : a.inv_dt) + lap * RT(a.inv_h2);
 #pragma unroll
     for (int qq = 0; qq < NV; ++qq)
       if (DIM == 2 || qq == rr) rsq[qq] += double(r) * double(r);
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
       const int off = DIM == 2 ? (y0 + rr) * N + x : x;
       rout[n * ns + off] = double(r);
     } else {
-      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(r);
+      comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) = T(r);
     }
   }
   __syncthreads();
@@ -216,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     for (int w = tid; w < K * P; w += NT) {
       const int p = w / K, k = w - (w / K) * K;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[zrow(k) * ES + p], z[zrow((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
       const size_t r1 = r0 + N;
@@ -236,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const int slot = DIM == 2 ? b : lev + q;  // [level][block] (NBL = 1 in 1D)
+      const int slot = DIM == 2 ? lev * NBL + strip : lev + q;  // [level][block] (NBL = 1 in 1D)
       a.part[size_t(slot) * PART_STRIDE + PART_RSQ] = rsq[q];
     }
   }
@@ -254,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
   constexpr int NV = DIM == 2 ? 1 : RB;
-  __shared__ __align__(16) cx<T> z[N * ES];
+  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
   __shared__ double red[NT * 4 * NV];
   __shared__ cx<T> s_tw[N], s_wi[N];
   table_to_lds<T, NT, N>(s_tw, dt.tw);
@@ -292,8 +306,8 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         const int p = w / K, k = w - (w / K) * K;
         cx<T> zk, zn;
         dct3_join(x1k[i], x2k[i], x1n[i], x2n[i], s_wi[k], zk, zn);
-        z[k * ES + p] = zk;
-        if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
+        z[zrow(k) * ES + p] = zk;
+        if (k > 0 && k < N / 2) z[zrow(N - k) * ES + p] = zn;
       }
     }
   }
@@ -325,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         const int idx = tid + (i0 + q) * NT;
         if (!(i0 + q < IT && (W % NT == 0 || idx < W))) continue;
         const int rr = idx / N, x = idx - (idx / N) * N;
-        const double del = double(comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n);
+        const double del = double(comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) * inv_n);
         const int n = DIM == 2 ? lev : lev + rr;
         const int off = DIM == 2 ? (y0 + rr) * N + x : x;
         const size_t gi = n * ns + off;
@@ -377,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
                                               DctTables<T> dt) {
   if (done && *done) return;
   constexpr int C = XB / 2, ES = C, NBX = N / XB, K = N / 2 + 1;
-  __shared__ __align__(16) cx<T> z[N * ES];
+  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
   __shared__ cx<T> s_tw[N], s_w[N];
   table_to_lds<T, NT, N>(s_tw, dt.tw);
   table_to_lds<T, NT, N>(s_w, INV ? dt.wi : dt.wq);
@@ -407,14 +421,14 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[(w / C) * ES + (w - (w / C) * C)] = x[i];
+      if (W % NT == 0 || w < W) z[zrow(w / C) * ES + (w - (w / C) * C)] = x[i];
     }
     __syncthreads();
     fft_lds<T, N, C, ES, NT, -1>(z, s_tw);
     for (int w = tid; w < K * C; w += NT) {
       const int k = w / C, c = w - (w / C) * C;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[zrow(k) * ES + c], z[zrow((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       *reinterpret_cast<cx<TO>*>(obase + size_t(k) * N + 2 * c) = mk(TO(x1k), TO(x2k));
       if (k > 0 && k < N / 2)
@@ -441,8 +455,8 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
         const int k = w / C, c = w - (w / C) * C;
         cx<T> zk, zn;
         dct3_join(xk[i].x, xk[i].y, xn[i].x, xn[i].y, s_w[k], zk, zn);
-        z[k * ES + c] = zk;
-        if (k > 0 && k < N / 2) z[(N - k) * ES + c] = zn;
+        z[zrow(k) * ES + c] = zk;
+        if (k > 0 && k < N / 2) z[zrow(N - k) * ES + c] = zn;
       }
     }
     __syncthreads();
@@ -450,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
     const T inv_n = T(1) / T(N);
     for (int w = tid; w < N * C; w += NT) {
       const int m = w / C, c = w - (w / C) * C;
-      const cx<T> v = scale(z[m * ES + c], inv_n);
+      const cx<T> v = scale(z[zrow(m) * ES + c], inv_n);
       *reinterpret_cast<cx<TO>*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) = mk(TO(v.x), TO(v.y));
     }
   }
@@ -461,20 +475,20 @@ template <typename T, int DIM, int N, int RB, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __restrict__ out, DctTables<T> dt) {
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int P = Gm::P, ES = Gm::ES, K = N / 2 + 1;
-  __shared__ __align__(16) cx<T> z[N * ES];
+  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
   const int tid = threadIdx.x;
   const size_t row0 = size_t(blockIdx.x) * RB;  // rows are contiguous in both 1D and 2D layouts
   if (!INV) {
     for (int idx = tid; idx < RB * N; idx += NT) {
       const int rr = idx / N, x = idx - (idx / N) * N;
-      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = in[(row0 + rr) * N + x];
+      comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) = in[(row0 + rr) * N + x];
     }
     __syncthreads();
     fft_lds<T, N, P, ES, NT, -1>(z, dt.tw);
     for (int w = tid; w < K * P; w += NT) {
       const int p = w / K, k = w - (w / K) * K;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], dt.wq[k], dt.wq[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[zrow(k) * ES + p], z[zrow((N - k) & (N - 1)) * ES + p], dt.wq[k], dt.wq[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
       out[r0 + k] = x1k;
@@ -490,15 +504,15 @@ __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __
       const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
       cx<T> zk, zn;
       dct3_join(in[r0 + k], in[r1 + k], k ? in[r0 + N - k] : T(0), k ? in[r1 + N - k] : T(0), dt.wi[k], zk, zn);
-      z[k * ES + p] = zk;
-      if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
+      z[zrow(k) * ES + p] = zk;
+      if (k > 0 && k < N / 2) z[zrow(N - k) * ES + p] = zn;
     }
     __syncthreads();
     fft_lds<T, N, P, ES, NT, +1>(z, dt.tw);
     const T inv_n = T(1) / T(N);
     for (int idx = tid; idx < RB * N; idx += NT) {
       const int rr = idx / N, x = idx - (idx / N) * N;
-      out[(row0 + rr) * N + x] = comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n;
+      out[(row0 + rr) * N + x] = comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) * inv_n;
     }
   }
 }
@@ -514,7 +528,7 @@ template <typename T, int NTT, int M, int NT>
 __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
   constexpr int C = M / 2;
-  __shared__ __align__(16) cx<T> z[NTT * C];
+  __shared__ __align__(16) cx<T> z[zrows(NTT) * C];
   __shared__ cx<T> s_tw[NTT];
   table_to_lds<T, NT, NTT>(s_tw, ta.tw);
   const int tid = threadIdx.x;
@@ -545,10 +559,10 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     for (int i = 0; i < IT2; ++i) {
       const int w = tid + i * NT;
       if (W2 % NT == 0 || w < W2) {
-        const int j = w / C2;
+        const int j = w / C2, c = w - (w / C2) * C2;
         const T s = ta.aj[j];
-        z[2 * w] = scale(mk(T(x[i].x), T(x[i].y)), s);
-        z[2 * w + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
+        z[zrow(j) * C + 2 * c] = scale(mk(T(x[i].x), T(x[i].y)), s);
+        z[zrow(j) * C + 2 * c + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
       }
     }
   } else {
@@ -565,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[w] = scale(x[i], ta.aj[w / C]);
+      if (W % NT == 0 || w < W) z[zrow(w / C) * C + (w - (w / C) * C)] = scale(x[i], ta.aj[w / C]);
     }
   }
   __syncthreads();
@@ -593,8 +607,8 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     if (w >= WD) continue;
     const int l = w / C, c = w - (w / C) * C;
     const int m = (NTT - l) & (NTT - 1);
-    const cx<T> zl = z[l * C + c];
-    const cx<T> zm = conj(z[m * C + c]);
+    const cx<T> zl = z[zrow(l) * C + c];
+    const cx<T> zm = conj(z[zrow(m) * C + c]);
     const cx<T> x1 = scale(add(zl, zm), T(0.5));
     const cx<T> x2 = scale(mul_mi(sub(zl, zm)), T(0.5));
     const T lk1 = lk1v[i], lk2 = lk2v[i];
@@ -605,8 +619,8 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2 * lk2, l1.y + pl.y * lk2 + ql.y * lk2 * lk2);
     const cx<T> y1 = cdiv(x1, s1);
     const cx<T> y2 = cdiv(x2, s2);
-    z[l * C + c] = add(y1, mul_i(y2));
-    if (m != l) z[m * C + c] = add(conj(y1), mul_i(conj(y2)));
+    z[zrow(l) * C + c] = add(y1, mul_i(y2));
+    if (m != l) z[zrow(m) * C + c] = add(conj(y1), mul_i(conj(y2)));
   }
   __syncthreads();
   fft_lds<T, NTT, C, C, NT, +1>(z, s_tw);
@@ -617,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       if (W2 % NT == 0 || w < W2) {
         const int j = w / C2, c = w - (w / C2) * C2;
         const T s = ta.aij[j];
-        const cx<T> a = scale(z[2 * w], s), b = scale(z[2 * w + 1], s);
+        const cx<T> a = scale(z[zrow(j) * C + 2 * c], s), b = scale(z[zrow(j) * C + 2 * c + 1], s);
         *reinterpret_cast<float4*>(S + j * ns + col0 + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
       }
     }
@@ -627,7 +641,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W % NT == 0 || w < W) {
         const int j = w / C, c = w - (w / C) * C;
-        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[zrow(j) * C + c], ta.aij[j]);
       }
     }
   }
@@ -648,7 +662,7 @@ struct CtrlPrev {
 };
 
 template <int NT>
-__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]);
+__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4], int lbeg, int lend);
 template <int NT>
 __device__ void finalize_control(const FinArgs& f, double* red, double (&v)[4], const CtrlPrev& c0);
 
@@ -678,7 +692,7 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
       v[3] = (rsq != rsq || rsq > v[3]) ? rsq : v[3];
     }
   } else {
-    finalize_levels_grouped<NT>(f, v);
+    finalize_levels_grouped<NT>(f, v, 0, f.nt);
   }
   finalize_control<NT>(f, red, v, c0);
 }
@@ -688,7 +702,7 @@ __device__ void finalize_body(const FinArgs& f, double* red) {
 // levels per wave and FL levels per lane in flight, and combines them with a
 // fixed xor-shuffle tree, so every sum is formed in the same order each run.
 template <int NT>
-__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]) {
+__device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4], int lbeg, int lend) {
   constexpr int NW = NT / 64, FL = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
@@ -696,13 +710,13 @@ __device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]) {
   while (g < gmax && g < 64) g <<= 1;
   const int lpw = 64 / g;  // levels per wave per step
   const int sub = lane / g, j = lane - (lane / g) * g;  // v: group leaders accumulate
-  for (int base = wave * lpw; base < f.nt; base += NW * lpw * FL) {
+  for (int base = lbeg + wave * lpw; base < lend; base += NW * lpw * FL) {
     double s[FL][4];
 #pragma unroll
     for (int u = 0; u < FL; ++u) {
       const int n = base + u * NW * lpw + sub;
       s[u][0] = s[u][1] = s[u][2] = s[u][3] = 0.0;
-      if (n < f.nt) {
+      if (n < lend) {
         for (int bb = j; bb < f.nbl; bb += g) {
           const double* pp = f.part + (size_t(n) * f.nbl + bb) * PART_STRIDE;
           s[u][0] += pp[PART_DSQ];
@@ -719,7 +733,7 @@ __device__ void finalize_levels_grouped(const FinArgs& f, double (&v)[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) s[u][q] += __shfl_xor(s[u][q], off, 64);
       const int n = base + u * NW * lpw + sub;
-      if (j == 0 && n < f.nt) {
+      if (j == 0 && n < lend) {
         v[0] = (s[u][0] != s[u][0] || s[u][0] > v[0]) ? s[u][0] : v[0];
         v[1] = (s[u][1] != s[u][1] || s[u][1] > v[1]) ? s[u][1] : v[1];
         v[2] += s[u][2];
@@ -799,6 +813,45 @@ __global__ __launch_bounds__(NT) void k_finalize(FinArgs f) {
   finalize_body<NT>(f, red);
 }
 constexpr int FIN_WIDE_SLOTS = 16384;
+
+// Many partials: first many workgroups, each reducing the block partials of
+// FIN_LEVELS consecutive levels to (max dsq, max usq, sum u2, max rsq) in
+// f.fin[group][4]; then one workgroup combines the groups in index order and
+// runs the stop rule.  Every sum keeps a fixed order.
+constexpr int FIN_LEVELS = 4;
+__global__ __launch_bounds__(256) void k_fin_levels(FinArgs f) {
+  if (f.ctrl->done) return;
+  __shared__ double red[4 * 4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int l0 = blockIdx.x * FIN_LEVELS;
+  finalize_levels_grouped<256>(f, v, l0, min(l0 + FIN_LEVELS, f.nt));
+  const bool ismax[4] = {true, true, false, true};
+  block_reduce_waves<256, 4>(red, v, ismax);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f.fin[size_t(blockIdx.x) * 4 + q] = v[q];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_finalize_groups(FinArgs f, int groups) {
+  if (f.ctrl->done) return;
+  __shared__ double red[4];
+  CtrlPrev c0{0, 0.0, 0.0};
+  if (threadIdx.x == 0) {
+    c0.iter = f.ctrl->iter;
+    c0.upd_prev = f.ctrl->upd_prev;
+    c0.upd_first = f.ctrl->upd_first;
+  }
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < groups; g += 64) {
+    const double* p = f.fin + size_t(g) * 4;
+    v[0] = (p[0] != p[0] || p[0] > v[0]) ? p[0] : v[0];
+    v[1] = (p[1] != p[1] || p[1] > v[1]) ? p[1] : v[1];
+    v[2] += p[2];
+    v[3] = (p[3] != p[3] || p[3] > v[3]) ? p[3] : v[3];
+  }
+  finalize_control<64>(f, red, v, c0);
+}
 
 // Control record reset and the first iteration's c_bar = mean(3 u^2) of the
 // initial guess (CH operators only): k_init_part writes workgroup partial
@@ -983,14 +1036,6 @@ struct row_fwd_cfg {
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
-// Tuning switch: PINT_ROWS_FWD=wide selects the inverse pass's block height.
-static bool rows_fwd_wide() {
-  static const bool wide = [] {
-    const char* s = std::getenv("PINT_ROWS_FWD");
-    return s && std::strcmp(s, "wide") == 0;
-  }();
-  return wide;
-}
 // Column-pass tile width and threads.
 // Columns per block: 32, or 16 for FP64 at N >= 256, where 32 columns take
 // 72-144 KB of LDS (C5 forward pass: 0.89 -> 0.62 ms); FP32 measured no gain.
@@ -1016,15 +1061,14 @@ int rows_blocks_per_level(int dim, int n) {
 
 int rows_fwd_blocks_per_level(int dim, int n) {
   if (dim != 2) return 1;
-  const bool w = rows_fwd_wide();
   switch (n) {
     case 8: return row_fwd_cfg<2, 8, false>::NBL;
     case 16: return row_fwd_cfg<2, 16, false>::NBL;
     case 32: return row_fwd_cfg<2, 32, false>::NBL;
     case 64: return row_fwd_cfg<2, 64, false>::NBL;
     case 128: return row_fwd_cfg<2, 128, false>::NBL;
-    case 256: return w ? row_fwd_cfg<2, 256, true>::NBL : row_fwd_cfg<2, 256, false>::NBL;
-    case 512: return w ? row_fwd_cfg<2, 512, true>::NBL : row_fwd_cfg<2, 512, false>::NBL;
+    case 256: return row_fwd_cfg<2, 256, false>::NBL;
+    case 512: return row_fwd_cfg<2, 512, false>::NBL;
     default: return 0;
   }
 }
@@ -1034,9 +1078,21 @@ int rows_levels_per_block(int dim, int n) {
   return dim == 1 ? row_cfg<1, 8>::RB : 1;
 }
 
+// Block order of the forward row pass: level-pipelined per XCD (see
+// k_rows_fwd) unless PINT_ROWS_ORDER=linear.
+static int rows_xcd_order() {
+  static const int v = [] {
+    const char* s = std::getenv("PINT_ROWS_ORDER");
+    return (s && std::strcmp(s, "linear") == 0) ? 0 : 1;
+  }();
+  return v;
+}
+
 template <typename T, typename TO, int DIM, int N, bool WIDE, typename RT>
-static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
+static hipError_t launch_rows_fwd_w(const ResidArgs& a0, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
+  ResidArgs a = a0;
+  a.xcd_order = rows_xcd_order();
   using C = row_fwd_cfg<DIM, N, WIDE>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)
@@ -1052,8 +1108,6 @@ static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, con
 template <typename T, typename TO, int DIM, int N, typename RT>
 static hipError_t launch_rows_fwd_n(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
-  if (DIM == 2 && N >= 256 && rows_fwd_wide())
-    return launch_rows_fwd_w<T, TO, DIM, N, true, RT>(a, S, rout, dt, nt, mode, st);
   return launch_rows_fwd_w<T, TO, DIM, N, false, RT>(a, S, rout, dt, nt, mode, st);
 }
 
@@ -1229,12 +1283,30 @@ hipError_t launch_time(int nt, T* S, const TimeArgs<T>& ta, hipStream_t st) {
   }
 }
 
+int finalize_groups(int nt, int nbl, int nbl_f) {
+  const int gmax = nbl > nbl_f ? nbl : nbl_f;
+  return size_t(nt) * gmax > size_t(FIN_WIDE_SLOTS) ? (nt + FIN_LEVELS - 1) / FIN_LEVELS : 0;
+}
+
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st) {
-  const int gmax = f.nbl > f.nbl_f ? f.nbl : f.nbl_f;
-  if (size_t(f.nt) * gmax > size_t(FIN_WIDE_SLOTS))
-    PINT_LAUNCH(k_finalize<1024>, dim3(1), dim3(1024), 0, st, f);
-  else
+  const int groups = finalize_groups(f.nt, f.nbl, f.nbl_f);
+  if (groups > 0) {
+    if (!f.fin) return hipErrorInvalidValue;
+    // stage timing: the start event on the first kernel, the stop event on the second
+    hipEvent_t e0 = g_launch_ev0, e1 = g_launch_ev1;
+    g_launch_ev0 = g_launch_ev1 = nullptr;
+    if (e0)
+      hipExtLaunchKernelGGL(k_fin_levels, dim3(groups), dim3(256), 0, st, e0, nullptr, 0, f);
+    else
+      hipLaunchKernelGGL(k_fin_levels, dim3(groups), dim3(256), 0, st, f);
+    PINT_CHECK_LAUNCH();
+    if (e1)
+      hipExtLaunchKernelGGL(k_finalize_groups, dim3(1), dim3(64), 0, st, nullptr, e1, 0, f, groups);
+    else
+      hipLaunchKernelGGL(k_finalize_groups, dim3(1), dim3(64), 0, st, f, groups);
+  } else {
     PINT_LAUNCH(k_finalize<256>, dim3(1), dim3(256), 0, st, f);
+  }
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }

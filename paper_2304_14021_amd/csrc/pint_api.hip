@@ -50,6 +50,9 @@ struct pint_plan {
   bool mixed;  // FP64 forward spatial transform, FP32 time solve and inverse
   int dense = -1;  // DenseKind of the time contraction on the matrix cores, -1: FFT path
   bool norefine = false;  // residual and iterate in FP32 (no refinement)
+  bool direct = false;    // nonuniform steps: direct diagonalization of the time-step pencil
+  std::vector<double> dts;  // the steps (direct only)
+  size_t off_dts = 0, off_idts = 0, off_v64 = 0, off_w64 = 0;  // direct tables in the block
   std::string err;
 
   // device tables (one allocation), FP64 then FP32 copies
@@ -132,6 +135,7 @@ double mu_min(const pint_problem& p, int dim, int n, double h) {
 
 // Kind of dense time contraction a problem asks for (-1: the FFT path).
 int dense_kind_of(const pint_problem* p) {
+  if (p->dts) return p->precision == PINT_PREC_FP64 ? -1 : DK_F32;  // direct: FP32 MFMA or FP64 vector
   if (p->precision == PINT_PREC_BF16_REFINE || p->precision == PINT_PREC_BF16_NOREFINE)
     return (p->flags & PINT_FLAG_BF16_SPLIT) ? DK_BF16X3 : DK_BF16;
   if (p->time_path == PINT_TIME_DENSE) return DK_F32;
@@ -149,13 +153,37 @@ int validate(const pint_problem* p, std::string* err) {
   if (p->dim == 1 && p->ny != 1 && p->ny != 0) return set_err(err, PINT_EINVAL, "1D problems need ny == 1");
   if (!is_pow2(p->nt) || p->nt < 4 || p->nt > 1024)
     return set_err(err, PINT_EINVAL, "nt must be a power of two in [4, 1024]");
-  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return set_err(err, PINT_EINVAL, "dt must be > 0");
+  if (!p->dts && (!(p->dt > 0.0) || !std::isfinite(p->dt))) return set_err(err, PINT_EINVAL, "dt must be > 0");
+  if (p->dts) {
+    // direct diagonalization of the time-step pencil (nonuniform steps)
+    std::vector<double> st(p->dts, p->dts + p->nt);
+    for (double x : st)
+      if (!(x > 0.0) || !std::isfinite(x)) return set_err(err, PINT_EINVAL, "dts: every step must be > 0");
+    std::sort(st.begin(), st.end());
+    for (size_t i = 1; i < st.size(); ++i)
+      if (!(st[i] - st[i - 1] > 1e-12 * st[i]))
+        return set_err(err, PINT_EINVAL,
+                       "dts: the steps must be pairwise distinct (equal steps make the time-step pencil "
+                       "defective; use the uniform-step path)");
+    if (p->op == PINT_OP_CH_EYRE)
+      return set_err(err, PINT_EINVAL, "nonuniform steps: the Eyre scheme is not supported");
+    if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED)
+      return set_err(err, PINT_EINVAL, "nonuniform steps: precision must be FP64, FP32_REFINE or MIXED");
+    if (p->time_path == PINT_TIME_FFT)
+      return set_err(err, PINT_EINVAL, "nonuniform steps: the time solve is the direct contraction, not the FFT");
+    if (p->nt < 32) return set_err(err, PINT_EINVAL, "nonuniform steps need nt >= 32");
+    const int ns = p->dim == 2 ? p->nx * p->nx : p->nx;
+    if (ns % dense_cols_per_block(p->nt) != 0 || ns % 32 != 0)
+      return set_err(err, PINT_EINVAL, "nonuniform steps: N_s must be a multiple of " +
+                                           std::to_string(std::max(32, dense_cols_per_block(p->nt))));
+  }
   const bool linear = p->op == PINT_OP_BIHARMONIC || p->op == PINT_OP_LINEAR_CH;
   if (linear && !(p->theta == 1.0 || p->theta == 0.5)) return set_err(err, PINT_EINVAL, "theta must be 1 or 0.5");
   if (!linear && p->theta != 1.0 && p->theta != 0.0)
     return set_err(err, PINT_EINVAL, "the CH schemes are backward Euler (theta = 1)");
   if (p->op != PINT_OP_BIHARMONIC && !(p->eps > 0.0)) return set_err(err, PINT_EINVAL, "eps must be > 0");
-  if (!(p->alpha >= 0.0 && p->alpha < 1.0)) return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
+  if (!p->dts && !(p->alpha >= 0.0 && p->alpha < 1.0))
+    return set_err(err, PINT_EINVAL, "alpha must be in (0, 1) (0 = auto)");
   if (p->precision != PINT_PREC_FP64 && p->precision != PINT_PREC_FP32_REFINE && p->precision != PINT_PREC_MIXED &&
       p->precision != PINT_PREC_BF16_REFINE && p->precision != PINT_PREC_FP32_NOREFINE &&
       p->precision != PINT_PREC_BF16_NOREFINE)
@@ -169,7 +197,7 @@ int validate(const pint_problem* p, std::string* err) {
   if ((p->precision == PINT_PREC_BF16_REFINE || p->precision == PINT_PREC_BF16_NOREFINE) &&
       p->time_path == PINT_TIME_FFT)
     return set_err(err, PINT_EINVAL, "BF16 is a precision of the dense time contraction, not of the FFT path");
-  if (dense_kind_of(p) >= 0) {
+  if (dense_kind_of(p) >= 0 && !p->dts) {
     const int nb = dense_cols_per_block(p->nt);
     const int ns = p->dim == 2 ? p->nx * p->nx : p->nx;
     if (nb == 0 || ns % nb != 0)
@@ -186,7 +214,7 @@ int validate(const pint_problem* p, std::string* err) {
 void build_tables(pint_plan* pl, HostTables& t) {
   const int n = pl->n, nt = pl->nt;
   const double h = pl->h, dt = pl->p.dt, a = pl->a, th = pl->p.theta;
-  const double la = std::log(pl->alpha) / nt;  // log a
+  const double la = pl->direct ? 0.0 : std::log(pl->alpha) / nt;  // log a (no alpha for direct)
   t.tw_s.resize(n);
   t.wq.resize(n);
   t.wi.resize(n);
@@ -230,6 +258,18 @@ void build_tables(pint_plan* pl, HostTables& t) {
         t.pco[l] = a * w;
         t.qco[l] = e2;
         break;
+    }
+    if (pl->direct) {
+      // direct diagonalization: row j of the contraction is eigen-coordinate
+      // j, divided by d_j + p lam + q lam^2 with d_j = 1/(theta dt_j) from the
+      // GPU eigendecomposition (lam1 is filled there) and the operator's
+      // spatial coefficients (the theta of the pencil sits in d_j and C)
+      t.lam1[l] = 0.0;
+      switch (pl->p.op) {
+        case PINT_OP_BIHARMONIC: t.pco[l] = 0.0; t.qco[l] = 1.0; break;
+        case PINT_OP_LINEAR_CH: t.pco[l] = b2; t.qco[l] = e2; break;
+        default: t.pco[l] = 1.0; t.qco[l] = e2; break;  // CH: (1 - c_bar) lam + eps^2 lam^2
+      }
     }
     t.aj[l] = std::exp(la * l);
     t.aij[l] = std::exp(-la * l) / nt;
@@ -365,6 +405,21 @@ void put_dense(std::vector<unsigned char>& buf, const pint_plan* pl, const size_
   }
 }
 
+// Direct diagonalization: the steps and 1/dt_n (FP64, for the residual) and
+// room for the FP64 eigenvector matrices V [n][j] and W [j][n], which the GPU
+// computes (k_eig_steps) after the upload.
+void reserve_direct(std::vector<unsigned char>& buf, pint_plan* pl) {
+  const int nt = pl->nt;
+  std::vector<double> idts(nt);
+  for (int i = 0; i < nt; ++i) idts[i] = 1.0 / pl->dts[i];
+  pl->off_dts = put_re<double>(buf, buf.size(), pl->dts);
+  pl->off_idts = put_re<double>(buf, buf.size(), idts);
+  pl->off_v64 = align256(buf.size());
+  buf.resize(pl->off_v64 + size_t(nt) * nt * 8);
+  pl->off_w64 = align256(buf.size());
+  buf.resize(pl->off_w64 + size_t(nt) * nt * 8);
+}
+
 void store_offs(const Offs& o, size_t* dst) {
   const size_t v[11] = {o.tw_s, o.wq, o.wi, o.tw_t, o.lam1, o.pco, o.qco, o.aj, o.aij, o.lamx, o.lamy};
   for (int i = 0; i < 11; ++i) dst[i] = v[i];
@@ -398,6 +453,7 @@ struct Work {
   void* S;    // spectral scratch in the working type W
   void* S64;  // FP64 forward-transform scratch (mixed precision only)
   double* part;
+  double* fin;  // first-stage results of the two-stage control reduction
   Ctrl* ctrl;
 };
 
@@ -411,8 +467,11 @@ size_t part_bytes(const pint_plan* pl) {
 size_t s_bytes(const pint_plan* pl) { return align256((size_t)pl->nt * pl->ns * (pl->fp64 ? 8 : 4)); }
 size_t s64_bytes(const pint_plan* pl) { return pl->mixed ? align256((size_t)pl->nt * pl->ns * 8) : 0; }
 
+size_t fin_bytes(const pint_plan* pl) {
+  return align256(size_t(std::max(1, finalize_groups(pl->nt, pl->nbl, pl->nbl_f))) * 4 * sizeof(double));
+}
 size_t work_size(const pint_plan* pl) {
-  return s_bytes(pl) + s64_bytes(pl) + part_bytes(pl) + align256(sizeof(Ctrl));
+  return s_bytes(pl) + s64_bytes(pl) + part_bytes(pl) + fin_bytes(pl) + align256(sizeof(Ctrl));
 }
 
 int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
@@ -427,6 +486,8 @@ int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
   b += s64_bytes(pl);
   w.part = reinterpret_cast<double*>(b);
   b += part_bytes(pl);
+  w.fin = reinterpret_cast<double*>(b);
+  b += fin_bytes(pl);
   w.ctrl = reinterpret_cast<Ctrl*>(b);
   return PINT_OK;
 }
@@ -467,6 +528,8 @@ template <typename T>
 hipError_t launch_time_any(const pint_plan* pl, T* S, const TimeArgs<T>& ta, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
     if (pl->dense >= 0) return launch_time_dense(pl->dense, pl->nt, S, ta, pl->dargs, st);
+  } else {
+    if (pl->direct) return launch_time_direct64(pl->nt, S, ta, pl->dargs, st);
   }
   return launch_time<T>(pl->nt, S, ta, st);
 }
@@ -483,7 +546,7 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.part = w.part;
   ra.done = &w.ctrl->done;
   ra.bcast = bcast ? 1 : 0;
-  FinArgs fa{w.ctrl, host, w.part, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->norefine ? 1 : 0,
+  FinArgs fa{w.ctrl, host, w.part, w.fin, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->norefine ? 1 : 0,
              pl->dof, pl->rtol, pl->safety};
   UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0, pl->norefine ? 1 : 0};
   T* S = static_cast<T*>(w.S);
@@ -602,6 +665,11 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   pl->mixed = p->precision == PINT_PREC_MIXED || p->precision == PINT_PREC_BF16_REFINE;
   pl->dense = dense_kind_of(p);
   pl->norefine = p->precision == PINT_PREC_FP32_NOREFINE || p->precision == PINT_PREC_BF16_NOREFINE;
+  pl->direct = p->dts != nullptr;
+  if (pl->direct) {
+    pl->dts.assign(p->dts, p->dts + p->nt);
+    pl->p.dts = nullptr;  // the caller's array is not kept
+  }
   pl->nbl = rows_blocks_per_level(pl->dim, pl->n);
   pl->nbl_f = rows_fwd_blocks_per_level(pl->dim, pl->n);
   if (pl->nt % rows_levels_per_block(pl->dim, pl->n) != 0) {
@@ -615,7 +683,8 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   // (fully discrete analysis of Section 2.2, thm3; thm6 for the spinodal
   // case), R = R_theta(dt mu_min).  Require alpha R^{N_t} < 1/2.
   const double mmin = mu_min(pl->p, pl->dim, pl->n, pl->h);
-  const double z = p->dt * mmin;
+  const double dt_max = pl->direct ? *std::max_element(pl->dts.begin(), pl->dts.end()) : p->dt;
+  const double z = dt_max * mmin;
   const double th = pl->p.theta;
   const double R = (1.0 - (1.0 - th) * z) / (1.0 + th * z);
   if (!(1.0 + th * z > 0.0)) {
@@ -623,7 +692,9 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
     return set_err(nullptr, PINT_EINVAL, "1 + theta dt mu_min <= 0: the sequential scheme is singular");
   }
   const double RN = std::pow(std::fabs(R) > 1.0 ? std::fabs(R) : 1.0, pl->nt);
-  if (p->alpha == 0.0) {
+  if (pl->direct) {
+    pl->alpha = 0.0;  // no alpha-circulant preconditioner: the pencil is diagonalized directly
+  } else if (p->alpha == 0.0) {
     double al = 1e-3;
     if (al * RN > 0.1) al = 0.1 / RN;
     pl->alpha = al;
@@ -636,7 +707,7 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
     pl->alpha = p->alpha;
   }
   pl->p.alpha = pl->alpha;
-  pl->a = std::exp(std::log(pl->alpha) / pl->nt);
+  pl->a = pl->direct ? 1.0 : std::exp(std::log(pl->alpha) / pl->nt);
 
   // residual coefficients
   ResidArgs& ra = pl->ra;
@@ -656,8 +727,9 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
   std::vector<unsigned char>& buf = pl->host_tab;
   store_offs(put_all<double>(buf, t), pl->offs_d);
   store_offs(put_all<float>(buf, t), pl->offs_f);
-  reserve_dense(buf, pl->dense, pl->nt, pl->offs_w);
-  if (pl->dense >= 0) put_dense(buf, pl, pl->offs_w);
+  reserve_dense(buf, pl->dense >= 0 ? pl->dense : (pl->direct ? DK_F32 : -1), pl->nt, pl->offs_w);
+  if (pl->dense >= 0 && !pl->direct) put_dense(buf, pl, pl->offs_w);
+  if (pl->direct) reserve_direct(buf, pl);
   pl->tab_bytes = align256(buf.size());
   if (!opts.defer_tables) {
     void* mem = opts.d_tables;
@@ -675,7 +747,16 @@ int plan_create_ex(const pint_problem* p, const PlanOpts& opts, pint_plan** out)
         delete pl;
         return rc;
       }
-      plan_bind_tables(pl, mem, nullptr, false);
+      rc = plan_bind_tables(pl, mem, nullptr, false);
+      if (!rc && pl->direct) {
+        // the eigendecomposition ran on the null stream: finish it here
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = hip_fail(nullptr, e, "time-step eigendecomposition");
+      }
+      if (rc) {
+        delete pl;
+        return rc;
+      }
     } else {
       rc = plan_bind_tables(pl, mem, opts.stream, true);
       if (rc) {
@@ -708,7 +789,22 @@ int plan_bind_tables(pint_plan* pl, void* d_mem, hipStream_t st, bool copy) {
   bind<double>(load_offs(pl->offs_d), base, pl, pl->dtd, pl->tad);
   bind<float>(load_offs(pl->offs_f), base, pl, pl->dtf, pl->taf);
   pl->dargs = DenseArgs{};
-  if (pl->dense == DK_F32) {
+  pl->ra.inv_dts = nullptr;
+  if (pl->direct) {
+    // the FP64 eigendecomposition of the time-step pencil, on the GPU
+    pl->dargs.direct = 1;
+    pl->dargs.wf = reinterpret_cast<const float*>(base + pl->offs_w[0]);
+    pl->dargs.wb = reinterpret_cast<const float*>(base + pl->offs_w[1]);
+    pl->dargs.w64 = reinterpret_cast<const double*>(base + pl->off_w64);
+    pl->dargs.v64 = reinterpret_cast<const double*>(base + pl->off_v64);
+    pl->ra.inv_dts = reinterpret_cast<const double*>(base + pl->off_idts);
+    EigArgs ea{reinterpret_cast<const double*>(base + pl->off_dts), pl->p.theta, pl->nt,
+               reinterpret_cast<double*>(base + pl->off_v64), reinterpret_cast<double*>(base + pl->off_w64),
+               reinterpret_cast<cx<double>*>(base + pl->offs_d[4]), reinterpret_cast<cx<float>*>(base + pl->offs_f[4]),
+               reinterpret_cast<float*>(base + pl->offs_w[0]), reinterpret_cast<float*>(base + pl->offs_w[1])};
+    const hipError_t e = launch_eig_steps(ea, st);
+    if (e != hipSuccess) return hip_fail(pl, e, "time-step eigendecomposition kernel");
+  } else if (pl->dense == DK_F32) {
     pl->dargs.wf = reinterpret_cast<const float*>(base + pl->offs_w[0]);
     pl->dargs.wb = reinterpret_cast<const float*>(base + pl->offs_w[1]);
   } else if (pl->dense >= 0) {
@@ -738,7 +834,15 @@ size_t plan_table_bytes(const pint_problem* p) {
   put_all<double>(buf, t);
   put_all<float>(buf, t);
   size_t offs[4];
-  reserve_dense(buf, dense_kind_of(p), p->nt, offs);
+  reserve_dense(buf, dense_kind_of(p) >= 0 ? dense_kind_of(p) : (p->dts ? DK_F32 : -1), p->nt, offs);
+  if (p->dts) {
+    // the layout of reserve_direct
+    std::vector<double> steps(p->nt);
+    put_re<double>(buf, buf.size(), steps);
+    put_re<double>(buf, buf.size(), steps);
+    buf.resize(align256(buf.size()) + size_t(p->nt) * p->nt * 8);
+    buf.resize(align256(buf.size()) + size_t(p->nt) * p->nt * 8);
+  }
   return align256(buf.size());
 }
 
@@ -998,6 +1102,21 @@ int pint_precond_apply(pint_plan* pl, const double* d_r, double* d_delta, double
       HIPCHK((launch_cols<float, float>(pl->n, S, S, nullptr, pl->dtf, pl->nt, true, st)), "inverse y-dct");
     HIPCHK(launch_rows_inv<float>(pl->dim, pl->n, ua, S, d_delta, pl->dtf, pl->nt, 1, st), "inverse x-dct");
   }
+  return PINT_OK;
+}
+
+int pint_time_eig(pint_plan* pl, double* h_V, double* h_W, double* h_d) {
+  if (!pl || !h_V || !h_W || !h_d) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  if (!pl->direct) return set_err(&pl->err, PINT_EINVAL, "the plan has uniform steps (no direct diagonalization)");
+  HIPCHK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  const unsigned char* base = static_cast<const unsigned char*>(pl->d_tab);
+  const size_t mat = size_t(pl->nt) * pl->nt * sizeof(double);
+  HIPCHK(hipMemcpy(h_V, base + pl->off_v64, mat, hipMemcpyDeviceToHost), "copy V");
+  HIPCHK(hipMemcpy(h_W, base + pl->off_w64, mat, hipMemcpyDeviceToHost), "copy W");
+  std::vector<std::complex<double>> lam(pl->nt);
+  HIPCHK(hipMemcpy(lam.data(), base + pl->offs_d[4], pl->nt * sizeof(std::complex<double>), hipMemcpyDeviceToHost),
+         "copy d");
+  for (int j = 0; j < pl->nt; ++j) h_d[j] = lam[j].real();
   return PINT_OK;
 }
 

@@ -64,15 +64,18 @@ struct ResidArgs {
   const double* U;
   double* part;     // [level][block] partials
   const int* done;
+  const double* inv_dts;  // 1/dt_n per level (nonuniform steps), or null: inv_dt
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
   int bcast;        // the iterate is u0 at every level (first iteration)
+  int xcd_order;    // level-pipelined block order per XCD (2D forward pass)
 };
 
 struct FinArgs {
   Ctrl* ctrl;
   Ctrl* host;  // pinned host mirror of the status fields (nullable)
   const double* part;
+  double* fin;   // per-group reductions [finalize_groups][4] (two-stage finalize)
   int nt, nbl, max_iter;
   int nbl_f;     // blocks per level of the forward row pass (its residual partials)
   int stagnate;  // unrefined mode: also stop once the update stops contracting
@@ -165,7 +168,33 @@ struct DenseArgs {
   const void* wf_lo;
   const void* wb_hi;
   const void* wb_lo;
+  // direct diagonalization (nonuniform steps): rows of W_f y are eigen-
+  // coordinates, each divided by the real lam1[j] + (pco[j] - c_bar) lam_k +
+  // qco[j] lam_k^2 instead of the complex pair divide
+  int direct;
+  const double* w64;  // FP64 W_f [j][n] (rows: left eigenvectors; FP64 path)
+  const double* v64;  // FP64 W_b [n][j] (columns: right eigenvectors)
 };
+// FP64 eigendecomposition of the theta-method time-step pencil with steps
+// dts (B = diag(1/dt)(I - S), C = theta I + (1-theta) S): eigenvalues
+// d_j = 1/(theta dt_j), unit-norm right eigenvectors V[:, j] and left ones
+// W[j, :] with W C V = I; also the FP32 transposed copies used by the
+// matrix-core contraction and the divide's eigenvalue tables.
+struct EigArgs {
+  const double* dts;
+  double theta;
+  int nt;
+  double* v64;        // [n][j]
+  double* w64;        // [j][n]
+  cx<double>* lam1d;  // d_j (real part)
+  cx<float>* lam1f;
+  float* wfT;         // [n][j] = W[j][n]
+  float* wbT;         // [j][n] = V[n][j]
+};
+hipError_t launch_eig_steps(const EigArgs& a, hipStream_t st);
+// Direct-diagonalization time solve in FP64 (vector FMA), in place on S.
+hipError_t launch_time_direct64(int nt, double* S, const TimeArgs<double>& ta, const DenseArgs& da,
+                                hipStream_t st);
 // Spatial modes per workgroup of the dense path (0 if N_t is too small).
 int dense_cols_per_block(int nt);
 hipError_t launch_time_dense(int kind, int nt, float* S, const TimeArgs<float>& ta, const DenseArgs& da,
@@ -173,6 +202,8 @@ hipError_t launch_time_dense(int kind, int nt, float* S, const TimeArgs<float>& 
 template <typename TI, typename TO>
 hipError_t launch_cast(const TI* in, TO* out, size_t n, hipStream_t st);
 hipError_t launch_finalize(const FinArgs& f, hipStream_t st);
+// Workgroups of the first stage of the control reduction (0: one stage).
+int finalize_groups(int nt, int nbl, int nbl_f);
 // Reset the control record (and its host mirror); with need_cbar, also the
 // first iteration's scalar averaged Jacobian.  The partials of the c_bar
 // reduction use a.part (nparts <= ceil(total / 4096) slots).

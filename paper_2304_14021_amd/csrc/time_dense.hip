@@ -192,6 +192,20 @@ __global__ __launch_bounds__(256) void k_time_dense(float* __restrict__ S, TimeA
 
   // divide the pairs (rows 2l, 2l+1) by sigma_{l,k} in the accumulators
   const float cbar = ta.cbar_mode ? float(ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0f;
+  if (da.direct) {
+    // direct diagonalization: row j holds eigen-coordinate j, divided by the
+    // real d_j + shift_k
+#pragma unroll
+    for (int q = 0; q < BPW; ++q) {
+      const int k = col0 + cb[q] * 32 + (lane & 31);
+      const float lk = ta.lamx[k % ta.nx] + ta.lamy[k / ta.nx];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = rb[q] * 32 + acc_row(i, lane);
+        acc[q][i] = acc[q][i] / (ta.lam1[r].x + (ta.pco[r].x - cbar) * lk + ta.qco[r].x * lk * lk);
+      }
+    }
+  } else
 #pragma unroll
   for (int q = 0; q < BPW; ++q) {
     const int k = col0 + cb[q] * 32 + (lane & 31);
@@ -254,9 +268,137 @@ hipError_t launch_dense_kind(int nt, float* S, const TimeArgs<float>& ta, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 eigendecomposition of the time-step pencil (B, C) of the theta-method
+// with steps dt_1..dt_{N_t}: B = diag(1/dt_n)(I - S), C = theta I + (1 - theta) S.
+// B - d C is lower bidiagonal, so d_j = 1/(theta dt_j) and thread j obtains
+//   the right eigenvector by forward substitution (v_n = 0 for n < j, v_j = 1,
+//   v_n = v_{n-1} (1/dt_n + d_j (1-theta)) / (1/dt_n - d_j theta) for n > j),
+//   the left one by backward substitution (w_m = 0 for m > j, w_j = 1,
+//   w_m = w_{m+1} (1/dt_{m+1} + d_j (1-theta)) / (1/dt_m - d_j theta), m < j),
+// then scales v to unit 2-norm and w so that w^T C v = 1 (w^T C v = theta w_j
+// v_j before scaling, the other terms vanish).  With distinct steps the
+// eigenvalues are distinct and (B + mu C)^{-1} = V (D + mu)^{-1} W.
+__global__ __launch_bounds__(64) void k_eig_steps(EigArgs a) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= a.nt) return;
+  const int nt = a.nt;
+  const double th = a.theta, omth = 1.0 - a.theta;
+  const double d = 1.0 / (th * a.dts[j]);
+  double v = 1.0, nrm2 = 1.0;
+  for (int n = j + 1; n < nt; ++n) {
+    const double idt = 1.0 / a.dts[n];
+    v = v * (idt + d * omth) / (idt - d * th);
+    nrm2 += v * v;
+  }
+  const double s = 1.0 / sqrt(nrm2);
+  // second pass: store the scaled right eigenvector
+  for (int n = 0; n < j; ++n) a.v64[size_t(n) * nt + j] = 0.0;
+  v = s;
+  a.v64[size_t(j) * nt + j] = v;
+  a.wbT[size_t(j) * nt + j] = float(v);
+  for (int n = j + 1; n < nt; ++n) {
+    const double idt = 1.0 / a.dts[n];
+    v = v * (idt + d * omth) / (idt - d * th);
+    a.v64[size_t(n) * nt + j] = v;
+    a.wbT[size_t(j) * nt + n] = float(v);
+  }
+  for (int n = 0; n < j; ++n) a.wbT[size_t(j) * nt + n] = 0.0f;
+  // left eigenvector, scaled by 1 / (theta s)
+  double w = 1.0 / (th * s);
+  a.w64[size_t(j) * nt + j] = w;
+  a.wfT[size_t(j) * nt + j] = float(w);
+  for (int m = j - 1; m >= 0; --m) {
+    w = w * (1.0 / a.dts[m + 1] + d * omth) / (1.0 / a.dts[m] - d * th);
+    a.w64[size_t(j) * nt + m] = w;
+    a.wfT[size_t(m) * nt + j] = float(w);
+  }
+  for (int m = j + 1; m < nt; ++m) {
+    a.w64[size_t(j) * nt + m] = 0.0;
+    a.wfT[size_t(m) * nt + j] = 0.0f;
+  }
+  a.lam1d[j] = mk(d, 0.0);
+  a.lam1f[j] = mk(float(d), 0.0f);
+}
+
+// Direct-diagonalization time solve in FP64: per spatial mode k (a column of
+// S), y = W x, y_j /= d_j + shift_k, x = V y.  One workgroup takes NB modes;
+// the tile and the intermediate stay in LDS; thread (row group g, column c)
+// accumulates rows g, g + NG, ... of its column.
+template <int NTT>
+__global__ __launch_bounds__(256) void k_time_direct64(double* __restrict__ S, TimeArgs<double> ta, DenseArgs da) {
+  if (ta.done && *ta.done) return;
+  constexpr int NB = NTT >= 512 ? 8 : (NTT >= 256 ? 16 : 32);
+  constexpr int NG = 256 / NB, R = NTT / NG;
+  __shared__ double xs[NTT * NB];
+  const int tid = threadIdx.x, c = tid % NB, g = tid / NB;
+  const size_t col0 = size_t(blockIdx.x) * NB;
+  const size_t ns = ta.ns;
+  for (int w = tid; w < NTT * NB; w += 256) {
+    const int n = w / NB, cc = w - (w / NB) * NB;
+    xs[w] = S[size_t(n) * ns + col0 + cc];
+  }
+  __syncthreads();
+  const double cbar = ta.cbar_mode ? (ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0;
+  const size_t k = col0 + c;
+  const double lk = ta.lamx[k % ta.nx] + ta.lamy[k / ta.nx];
+  double acc[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = 0.0;
+  for (int n = 0; n < NTT; ++n) {
+    const double x = xs[n * NB + c];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] += da.w64[size_t(g + i * NG) * NTT + n] * x;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = g + i * NG;
+    acc[i] /= ta.lam1[j].x + (ta.pco[j].x - cbar) * lk + ta.qco[j].x * lk * lk;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R; ++i) xs[(g + i * NG) * NB + c] = acc[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = 0.0;
+  for (int j = 0; j < NTT; ++j) {
+    const double y = xs[j * NB + c];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] += da.v64[size_t(g + i * NG) * NTT + j] * y;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) S[size_t(g + i * NG) * ns + k] = acc[i];
+}
+
+template <int NTT>
+hipError_t launch_direct64_nt(double* S, const TimeArgs<double>& ta, const DenseArgs& da, hipStream_t st) {
+  constexpr int NB = NTT >= 512 ? 8 : (NTT >= 256 ? 16 : 32);
+  if (ta.ns % NB != 0) return hipErrorInvalidValue;
+  PINT_LAUNCH((k_time_direct64<NTT>), dim3(ta.ns / NB), dim3(256), 0, st, S, ta, da);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int dense_cols_per_block(int nt) { return nt >= 32 ? dense_nb(nt) : 0; }
+
+hipError_t launch_eig_steps(const EigArgs& a, hipStream_t st) {
+  PINT_LAUNCH(k_eig_steps, dim3((a.nt + 63) / 64), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_direct64(int nt, double* S, const TimeArgs<double>& ta, const DenseArgs& da,
+                                hipStream_t st) {
+  switch (nt) {
+    case 32: return launch_direct64_nt<32>(S, ta, da, st);
+    case 64: return launch_direct64_nt<64>(S, ta, da, st);
+    case 128: return launch_direct64_nt<128>(S, ta, da, st);
+    case 256: return launch_direct64_nt<256>(S, ta, da, st);
+    case 512: return launch_direct64_nt<512>(S, ta, da, st);
+    case 1024: return launch_direct64_nt<1024>(S, ta, da, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_time_dense(int kind, int nt, float* S, const TimeArgs<float>& ta, const DenseArgs& da,
                              hipStream_t st) {

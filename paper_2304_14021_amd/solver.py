@@ -27,7 +27,7 @@ class Solver:
     def __init__(self, op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1.0, eps: float = 1.0,
                  beta: float = 0.0, alpha: float = 1e-3, precision: str = "fp32", time_path: str = "auto",
                  rtol: float = 1e-10, max_iter: int = 30, broadcast_u0: bool = True, stage_timing: bool = False,
-                 graph: bool = False, invariants: bool = False, device=None):
+                 graph: bool = False, invariants: bool = False, dts=None, device=None):
         _require_gpu()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         flags = (_pint.FLAG_INIT_BROADCAST_U0 if broadcast_u0 else 0) | (_pint.FLAG_STAGE_TIMING if stage_timing else 0)
@@ -42,13 +42,16 @@ class Solver:
         with torch.cuda.device(self.device):
             self.plan = _pint.Plan(_pint.make_problem(op, dim, n, nt, dt, theta=theta, eps=eps, beta=beta,
                                                       alpha=alpha, precision=precision, time_path=time_path,
-                                                      rtol=rtol, max_iter=max_iter, flags=flags))
+                                                      rtol=rtol, max_iter=max_iter, flags=flags, dts=dts))
             self.work = torch.empty(self.plan.work_bytes + 256, dtype=torch.uint8, device=self.device)
         self.alpha = self.plan.alpha
 
     @classmethod
     def for_problem(cls, p, **kw):
-        """Build from any object with the fields op, dim, n, nt, dt, theta, eps, beta, alpha."""
+        """Build from any object with the fields op, dim, n, nt, dt, theta, eps, beta, alpha.  A problem
+        with nonuniform steps (a field q != 1) needs its steps passed as dts=."""
+        if getattr(p, "q", 1.0) != 1.0 and kw.get("dts") is None:
+            raise ValueError("a problem with nonuniform steps needs dts=")
         return cls(p.op, p.dim, p.n, p.nt, p.dt, theta=p.theta, eps=p.eps, beta=p.beta, alpha=p.alpha, **kw)
 
     def _work_ptr(self):
@@ -110,6 +113,11 @@ class Solver:
         self.plan.precond_raw(r.data_ptr(), d.data_ptr(), c_bar, self._work_ptr(), self.plan.work_bytes,
                               self._stream())
         return d
+
+    def time_eig(self):
+        """(V, W, d): the plan's FP64 eigendecomposition of the time-step
+        pencil (nonuniform steps only), B V = C V diag(d), W C V = I."""
+        return self.plan.time_eig()
 
     def diagnostics(self, U: torch.Tensor):
         self._check(U, self.shape, "U")

@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 from paper_2304_14021_amd import _pint
@@ -77,3 +79,23 @@ def test_status_strings():
     lib = _pint.lib()
     for code in range(-8, 1):
         assert lib.dll.pint_status_string(code).startswith(b"PINT_")
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(dts=np.full(32, 1e-5)), "pairwise distinct"),
+    (dict(dts=np.r_[-1e-5, 1e-5 * 1.1 ** np.arange(1, 32)]), "> 0"),
+    (dict(op="ch_eyre"), "Eyre"),
+    (dict(precision="bf16"), "precision"),
+    (dict(time_path="fft"), "FFT"),
+    (dict(nt=16, dts=1e-6 * 1.2 ** np.arange(16)), "nt >= 32"),
+])
+def test_validation_rejects_bad_nonuniform_steps(kw, frag):
+    # checked before any device work (no GPU needed)
+    args = dict(op="linear_ch", dim=2, n=32, nt=32, dt=0.0, eps=0.05, beta=0.5, precision="mixed",
+                dts=1e-6 * 1.2 ** np.arange(32))
+    args.update(kw)
+    p = _pint.make_problem(**args)
+    with pytest.raises(_pint.PintError) as ei:
+        _pint.Plan(p)
+    assert ei.value.code == _pint.PINT_EINVAL
+    assert frag in str(ei.value)

@@ -1,65 +1,44 @@
-"""Full-size nonlinear CH configurations on the GPU.
+"""Full-size nonlinear CH configurations on the GPU, against stored data of
+the oracle's sequential solution (tests/golden/make_golden.py, CPU only; the
+comparison and its bounds are in tests/_golden.py): every level's 2-norm,
+four random projections of every level, 256 points at ~16 levels, and every
+level's discrete mass and energy.
 
 C3: 2D CH (PinT-I), eps = 0.01, 256^2 cells, 256 levels, dt = 1e-6,
-    u0 ~ U[-0.1, 0.1] (seed 3).  Checked against samples of the oracle's
-    sequential solution stored by tests/golden/make_golden.py: every per-level
-    2-norm, mass and energy, and 64 points at 8 levels.  A relative error of
-    1e-10 in the paper's L^inf(0,T; L^2) norm implies |e_n(x)| <= 1e-10
-    max_n ||u_n||_2 at every point, which is the bound used.
+    u0 ~ U[-0.1, 0.1] (seed 3).
 C5: 2D CH (PinT-I), eps = 0.0075, 512^2 cells, 1024 levels, dt = 1e-6,
-    u0 ~ U[-0.05, 0.05] (seed 5).  The whole sequential oracle would need
-    hours, so the oracle takes single steps (eq. fully-dis_CH) from the GPU's
-    own previous level at sampled levels, plus exact mass conservation and a
-    non-increasing energy.
+    u0 ~ U[-0.05, 0.05] (seed 5); also the oracle's single step from the
+    GPU's own previous level at sampled levels (a local check independent of
+    the stored data).
+Bar: relative error 1e-10 in the paper's L^inf(0,T; L^2) norm (Section 5).
 """
 import dataclasses
-import json
-import os
 
 import numpy as np
 import pytest
 
-from oracle import allatonce as aao
-from oracle import operators as ops
 from oracle import stepper
 from paper_2304_14021_amd import Solver
 from workloads import CONFIGS, initial_datum
+from tests import _golden
 from tests._gpu import dev, host, say, to_dev
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_samples.json")
 
 
-def _solve(name, prec, alpha=None):
+def _solve(name, prec, alpha=None, **kw):
     p = CONFIGS[name] if alpha is None else dataclasses.replace(CONFIGS[name], alpha=alpha)
     u0 = initial_datum(name)
-    s = Solver.for_problem(p, precision=prec, device=dev())
+    s = Solver.for_problem(p, precision=prec, device=dev(), **kw)
     Ud, rep = s.solve(to_dev(u0), raise_on_error=False)
     m, e = s.diagnostics(Ud)
     return p, u0, host(Ud), rep, host(m), host(e)
 
 
-# alpha = 1e-4: one outer iteration fewer than at the workload's 1e-3 (the
-# benchmark's choice for the nonlinear CH workloads)
-@pytest.mark.parametrize("prec,alpha", [("mixed", None), ("fp64", None), ("fp32", None), ("mixed", 1e-4)])
-def test_c3_against_oracle_samples(prec, alpha):
-    say(f"c3 {prec} alpha {alpha}")
-    g = json.load(open(GOLDEN))
-    p, u0, U, rep, m, e = _solve("c3", prec, alpha)
-    say(f"  status {rep['status']} iterations {rep['iterations']} updates {['%.1e' % x for x in rep['upd_hist']]}")
-    assert rep["status"] == 0
-    norms = np.sqrt(np.sum(U.reshape(p.nt, -1) ** 2, axis=1))
-    nref = np.array(g["norms"])
-    assert np.max(np.abs(norms - nref)) <= 1e-10 * np.max(nref)
-    bound = 1e-10 * np.max(nref)
-    pts = np.array(g["points"])
-    worst = 0.0
-    for lev, vals in g["samples"].items():
-        got = U[int(lev) - 1][pts[:, 0], pts[:, 1]]
-        worst = max(worst, float(np.max(np.abs(got - np.array(vals)))))
-    say(f"  worst sample error {worst:.2e} (bound {bound:.2e})")
-    assert worst <= bound
-    # invariants and the oracle's diagnostics
+def _check_golden(name, U, m, e):
+    g = _golden.load(name)
+    c = _golden.assert_within(U, g)
+    say(f"  deviation from the stored oracle data {c}")
     assert np.allclose(m, g["mass"], rtol=0, atol=1e-13 * max(1.0, abs(g["mass0"])))
     assert np.max(np.abs(m - g["mass0"])) <= 1e-13 * max(1.0, abs(g["mass0"]))
     assert np.allclose(e, g["energy"], rtol=1e-10, atol=0)
@@ -67,26 +46,34 @@ def test_c3_against_oracle_samples(prec, alpha):
     assert np.all(np.diff(e_all) <= 1e-13 * np.abs(e_all[1:]))
 
 
-@pytest.mark.parametrize("prec,alpha", [("mixed", None), ("mixed", 1e-4)])
-def test_c5_steps_mass_energy(prec, alpha):
-    say(f"c5 {prec} alpha {alpha}")
-    p, u0, U, rep, m, e = _solve("c5", prec, alpha)
+# alpha = 1e-4: one outer iteration fewer than at the workload's 1e-3 (the
+# benchmark's choice for the nonlinear CH workloads)
+@pytest.mark.parametrize("prec,alpha", [("mixed", None), ("fp64", None), ("fp32", None), ("mixed", 1e-4)])
+def test_c3_against_oracle_data(prec, alpha):
+    say(f"c3 {prec} alpha {alpha}")
+    p, u0, U, rep, m, e = _solve("c3", prec, alpha)
     say(f"  status {rep['status']} iterations {rep['iterations']} updates {['%.1e' % x for x in rep['upd_hist']]}")
     assert rep["status"] == 0
-    # Necessary condition of a 1e-10 relative L^inf(L^2) error: each level
-    # differs from the oracle's sequential step taken from the GPU's previous
-    # level by at most (1 + R) 1e-10 max_n ||u_n||, R the per-step growth
-    # bound (1 + dt mu_min)^{-1} <= 1.005 here.
+    _check_golden("c3", U, m, e)
+
+
+# The benchmark's paths at 512^2 x 1024: mixed and FP64 at alpha = 1e-4, the
+# BF16-split dense contraction at alpha = 1e-3 (its rounding grows like
+# u_bf16 / alpha, while alpha R^{N_t} stays well below 1/2).
+@pytest.mark.parametrize("prec,alpha,path", [("mixed", 1e-4, "auto"), ("fp64", 1e-4, "auto"),
+                                             ("mixed", None, "auto"), ("bf16x3", 1e-3, "dense")])
+def test_c5_against_oracle_data(prec, alpha, path):
+    say(f"c5 {prec} alpha {alpha} {path}")
+    p, u0, U, rep, m, e = _solve("c5", prec, alpha, time_path=path, max_iter=60)
+    say(f"  status {rep['status']} iterations {rep['iterations']} updates {['%.1e' % x for x in rep['upd_hist']]}")
+    assert rep["status"] == 0
+    _check_golden("c5", U, m, e)
+    # local check: the oracle's own step from the GPU's previous level
     unrm = np.max(np.sqrt(np.sum(U.reshape(p.nt, -1) ** 2, axis=1)))
     worst = 0.0
-    for n in (1, 2, 512, 1024):
+    for n in (1, 512, 1024):
         prev = u0 if n == 1 else U[n - 2]
         ref = stepper.ch_step_modal(prev, p.dt, p.eps)
         worst = max(worst, float(np.sqrt(np.sum((U[n - 1] - ref) ** 2))) / unrm)
     say(f"  worst local step defect {worst:.2e}")
     assert worst <= 2.01e-10
-    m0 = ops.mass(u0, p.h)
-    assert np.max(np.abs(m - m0)) <= 1e-13 * max(1.0, abs(m0))
-    e_all = np.concatenate([[ops.energy(u0, p.eps, p.h)], e])
-    assert np.all(np.diff(e_all) <= 1e-13 * np.abs(e_all[1:]))
-    assert np.allclose(e[::97], [ops.energy(U[n], p.eps, p.h) for n in range(0, p.nt, 97)], rtol=1e-12)

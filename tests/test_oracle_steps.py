@@ -117,9 +117,10 @@ def test_residual_with_steps(op):
         assert a.shape[0] == p.ns
 
 
-@pytest.mark.parametrize("op,c_bar", [("linear_ch", 0.0), ("biharmonic", 0.0), ("ch", 0.37)])
-def test_modal_solve_with_steps_equals_direct_solve(op, c_bar):
-    p = Problem(op=op, dim=2, n=6, nt=5, dt=1e-5, eps=0.07, beta=0.4, q=1.6)
+@pytest.mark.parametrize("op,c_bar,theta", [("linear_ch", 0.0, 1.0), ("biharmonic", 0.0, 1.0), ("ch", 0.37, 1.0),
+                                            ("linear_ch", 0.0, 0.5), ("biharmonic", 0.0, 0.5)])
+def test_modal_solve_with_steps_equals_direct_solve(op, c_bar, theta):
+    p = Problem(op=op, dim=2, n=6, nt=5, dt=1e-5, eps=0.07, beta=0.4, q=1.6, theta=theta)
     dts = time_steps(p)
     rng = np.random.default_rng(6)
     r = rng.standard_normal(p.shape)
@@ -128,7 +129,7 @@ def test_modal_solve_with_steps_equals_direct_solve(op, c_bar):
         a = ((1.0 - c_bar) * lap + p.eps ** 2 * (lap @ lap)).tocsr()
     else:
         a = ops.operator_a(op, 2, p.n, p.h, eps=p.eps, beta=p.beta)
-    direct = spla.spsolve(aao.allatonce_matrix_steps(a, dts, 1.0).tocsc(), r.reshape(-1)).reshape(r.shape)
+    direct = spla.spsolve(aao.allatonce_matrix_steps(a, dts, theta).tocsc(), r.reshape(-1)).reshape(r.shape)
     modal = aao.idct2(aao.time_solve_steps_modal(p, aao.dct2(r, 2), dts, c_bar), 2)
     assert np.max(np.abs(modal - direct)) < 1e-11 * np.max(np.abs(direct))
 

@@ -108,7 +108,7 @@ CONFIGS: Dict[str, Problem] = {
     # geometrically graded steps (1e-6 growing by 1.2 per level, T = 0.58):
     # the time-step matrix is no longer alpha-circulant and is diagonalized
     # directly (FP64 eigendecomposition, dense contraction on the matrix cores)
-    "c2g": Problem(op="linear_ch", dim=2, n=128, nt=64, dt=1e-6, eps=0.05, beta=0.5, alpha=0.0, q=1.2),
+    "c2g": Problem(op="linear_ch", dim=2, n=128, nt=64, dt=5e-8, eps=0.05, beta=0.5, alpha=0.0, q=1.2),
 }
 
 SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "c2g": 6}
