@@ -4,11 +4,8 @@
 // FFT per pair of sequences.
 //
 // Layout of the complex FFT scratch: element m of sequence p lives at
-// z[zrow(m) * ES + p] ("element-major"), ES >= P, with one padding row after
-// every 16 rows (zrow(m) = m + m/16; the buffer holds zrows(N) rows).
-// Consecutive threads take consecutive p, so the reads of a stage are
-// consecutive LDS words; the padding spreads the stride-R writes of a
-// Stockham stage (rows d + r Ns with d = R t + ...) over the LDS banks.
+// z[m * ES + p] ("element-major"), ES >= P.  Consecutive threads take
+// consecutive p, so every FFT stage reads and writes consecutive LDS words.
 // Each stage reads all of its inputs into registers, synchronizes, then
 // writes, so the transform runs in place in the same LDS buffer.
 //
@@ -19,9 +16,6 @@
 #include "device_common.hpp"
 
 namespace pint {
-
-__host__ __device__ constexpr int zrow(int m) { return m + (m >> 4); }
-__host__ __device__ constexpr int zrows(int n) { return n + n / 16; }
 
 // Radix-4 DFT of (x0, x1, x2, x3) in place; SIGN -1 forward, +1 inverse.
 template <typename T, int SIGN>
@@ -74,7 +68,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw
     if ((W % NT == 0) || w < W) {
       const int t = w / P, p = w - (w / P) * P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = z[zrow(t + r * (N / R)) * ES + p];
+      for (int r = 0; r < R; ++r) v[i][r] = z[(t + r * (N / R)) * ES + p];
       const int k = t & (Ns - 1);
       const int step = k * (N / (Ns * R));
 #pragma unroll
@@ -102,7 +96,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw
       const int k = t & (Ns - 1);
       const int d = (t - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[zrow(d + r * Ns) * ES + p] = v[i][r];
+      for (int r = 0; r < R; ++r) z[(d + r * Ns) * ES + p] = v[i][r];
     }
   }
   __syncthreads();

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (a.done && *a.done) return;
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
-  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = zrows(N) * ES * int(sizeof(cx<T>));
+  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
   constexpr int R0 = VB > ZB ? VB : ZB;
   constexpr int NV = DIM == 2 ? 1 : RB;
   constexpr int RED = NT * NV * 8;  // reduction scratch, reuses the G region
@@ -96,21 +96,8 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   }
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
-  int lev = DIM == 2 ? b / NBL : b * RB;
-  int strip = DIM == 2 ? b - (b / NBL) * NBL : 0;
-  if constexpr (DIM == 2 && NBL % 8 == 0) {
-    if (a.xcd_order) {
-      // Workgroups are dealt to the 8 XCDs round-robin.  XCD x takes the strips
-      // [x G, (x+1) G) (G = NBL / 8) of every level, level after level, so the
-      // halo rows shared by neighbouring strips and the rows of u_n that the
-      // next level's blocks read again as u_{n-1} meet in one L2.
-      constexpr int G = NBL / 8;
-      const int x = b & 7, j = b >> 3;
-      lev = j / G;
-      strip = x * G + (j - (j / G) * G);
-    }
-  }
-  const int y0 = strip * RB;
+  const int lev = DIM == 2 ? b / NBL : b * RB;
+  const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
   const bool bc = a.bcast != 0;
   const double th = a.theta, omth = 1.0 - a.theta;
@@ -220,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
       const int off = DIM == 2 ? (y0 + rr) * N + x : x;
       rout[n * ns + off] = double(r);
     } else {
-      comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) = T(r);
+      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(r);
     }
   }
   __syncthreads();
@@ -230,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     for (int w = tid; w < K * P; w += NT) {
       const int p = w / K, k = w - (w / K) * K;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[zrow(k) * ES + p], z[zrow((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
       const size_t r1 = r0 + N;
@@ -250,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const int slot = DIM == 2 ? lev * NBL + strip : lev + q;  // [level][block] (NBL = 1 in 1D)
+      const int slot = DIM == 2 ? b : lev + q;  // [level][block] (NBL = 1 in 1D)
       a.part[size_t(slot) * PART_STRIDE + PART_RSQ] = rsq[q];
     }
   }
@@ -268,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
   constexpr int NV = DIM == 2 ? 1 : RB;
-  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
+  __shared__ __align__(16) cx<T> z[N * ES];
   __shared__ double red[NT * 4 * NV];
   __shared__ cx<T> s_tw[N], s_wi[N];
   table_to_lds<T, NT, N>(s_tw, dt.tw);
@@ -306,8 +293,8 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         const int p = w / K, k = w - (w / K) * K;
         cx<T> zk, zn;
         dct3_join(x1k[i], x2k[i], x1n[i], x2n[i], s_wi[k], zk, zn);
-        z[zrow(k) * ES + p] = zk;
-        if (k > 0 && k < N / 2) z[zrow(N - k) * ES + p] = zn;
+        z[k * ES + p] = zk;
+        if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
       }
     }
   }
@@ -339,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         const int idx = tid + (i0 + q) * NT;
         if (!(i0 + q < IT && (W % NT == 0 || idx < W))) continue;
         const int rr = idx / N, x = idx - (idx / N) * N;
-        const double del = double(comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) * inv_n);
+        const double del = double(comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n);
         const int n = DIM == 2 ? lev : lev + rr;
         const int off = DIM == 2 ? (y0 + rr) * N + x : x;
         const size_t gi = n * ns + off;
@@ -391,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
                                               DctTables<T> dt) {
   if (done && *done) return;
   constexpr int C = XB / 2, ES = C, NBX = N / XB, K = N / 2 + 1;
-  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
+  __shared__ __align__(16) cx<T> z[N * ES];
   __shared__ cx<T> s_tw[N], s_w[N];
   table_to_lds<T, NT, N>(s_tw, dt.tw);
   table_to_lds<T, NT, N>(s_w, INV ? dt.wi : dt.wq);
@@ -421,14 +408,14 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[zrow(w / C) * ES + (w - (w / C) * C)] = x[i];
+      if (W % NT == 0 || w < W) z[(w / C) * ES + (w - (w / C) * C)] = x[i];
     }
     __syncthreads();
     fft_lds<T, N, C, ES, NT, -1>(z, s_tw);
     for (int w = tid; w < K * C; w += NT) {
       const int k = w / C, c = w - (w / C) * C;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[zrow(k) * ES + c], z[zrow((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       *reinterpret_cast<cx<TO>*>(obase + size_t(k) * N + 2 * c) = mk(TO(x1k), TO(x2k));
       if (k > 0 && k < N / 2)
@@ -455,8 +442,8 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
         const int k = w / C, c = w - (w / C) * C;
         cx<T> zk, zn;
         dct3_join(xk[i].x, xk[i].y, xn[i].x, xn[i].y, s_w[k], zk, zn);
-        z[zrow(k) * ES + c] = zk;
-        if (k > 0 && k < N / 2) z[zrow(N - k) * ES + c] = zn;
+        z[k * ES + c] = zk;
+        if (k > 0 && k < N / 2) z[(N - k) * ES + c] = zn;
       }
     }
     __syncthreads();
@@ -464,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
     const T inv_n = T(1) / T(N);
     for (int w = tid; w < N * C; w += NT) {
       const int m = w / C, c = w - (w / C) * C;
-      const cx<T> v = scale(z[zrow(m) * ES + c], inv_n);
+      const cx<T> v = scale(z[m * ES + c], inv_n);
       *reinterpret_cast<cx<TO>*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) = mk(TO(v.x), TO(v.y));
     }
   }
@@ -475,20 +462,20 @@ template <typename T, int DIM, int N, int RB, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __restrict__ out, DctTables<T> dt) {
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int P = Gm::P, ES = Gm::ES, K = N / 2 + 1;
-  __shared__ __align__(16) cx<T> z[zrows(N) * ES];
+  __shared__ __align__(16) cx<T> z[N * ES];
   const int tid = threadIdx.x;
   const size_t row0 = size_t(blockIdx.x) * RB;  // rows are contiguous in both 1D and 2D layouts
   if (!INV) {
     for (int idx = tid; idx < RB * N; idx += NT) {
       const int rr = idx / N, x = idx - (idx / N) * N;
-      comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) = in[(row0 + rr) * N + x];
+      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = in[(row0 + rr) * N + x];
     }
     __syncthreads();
     fft_lds<T, N, P, ES, NT, -1>(z, dt.tw);
     for (int w = tid; w < K * P; w += NT) {
       const int p = w / K, k = w - (w / K) * K;
       T x1k, x2k, x1n, x2n;
-      dct2_split(z[zrow(k) * ES + p], z[zrow((N - k) & (N - 1)) * ES + p], dt.wq[k], dt.wq[(N - k) & (N - 1)], x1k, x2k,
+      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], dt.wq[k], dt.wq[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
       const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
       out[r0 + k] = x1k;
@@ -504,15 +491,15 @@ __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __
       const size_t r0 = (row0 + 2 * p) * N, r1 = r0 + N;
       cx<T> zk, zn;
       dct3_join(in[r0 + k], in[r1 + k], k ? in[r0 + N - k] : T(0), k ? in[r1 + N - k] : T(0), dt.wi[k], zk, zn);
-      z[zrow(k) * ES + p] = zk;
-      if (k > 0 && k < N / 2) z[zrow(N - k) * ES + p] = zn;
+      z[k * ES + p] = zk;
+      if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
     }
     __syncthreads();
     fft_lds<T, N, P, ES, NT, +1>(z, dt.tw);
     const T inv_n = T(1) / T(N);
     for (int idx = tid; idx < RB * N; idx += NT) {
       const int rr = idx / N, x = idx - (idx / N) * N;
-      out[(row0 + rr) * N + x] = comp(z[zrow(dct_iperm<N>(x)) * ES + (rr >> 1)], rr & 1) * inv_n;
+      out[(row0 + rr) * N + x] = comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n;
     }
   }
 }
@@ -528,7 +515,7 @@ template <typename T, int NTT, int M, int NT>
 __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
   constexpr int C = M / 2;
-  __shared__ __align__(16) cx<T> z[zrows(NTT) * C];
+  __shared__ __align__(16) cx<T> z[NTT * C];
   __shared__ cx<T> s_tw[NTT];
   table_to_lds<T, NT, NTT>(s_tw, ta.tw);
   const int tid = threadIdx.x;
@@ -559,10 +546,10 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     for (int i = 0; i < IT2; ++i) {
       const int w = tid + i * NT;
       if (W2 % NT == 0 || w < W2) {
-        const int j = w / C2, c = w - (w / C2) * C2;
+        const int j = w / C2;
         const T s = ta.aj[j];
-        z[zrow(j) * C + 2 * c] = scale(mk(T(x[i].x), T(x[i].y)), s);
-        z[zrow(j) * C + 2 * c + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
+        z[2 * w] = scale(mk(T(x[i].x), T(x[i].y)), s);
+        z[2 * w + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
       }
     }
   } else {
@@ -579,7 +566,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[zrow(w / C) * C + (w - (w / C) * C)] = scale(x[i], ta.aj[w / C]);
+      if (W % NT == 0 || w < W) z[w] = scale(x[i], ta.aj[w / C]);
     }
   }
   __syncthreads();
@@ -607,8 +594,8 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     if (w >= WD) continue;
     const int l = w / C, c = w - (w / C) * C;
     const int m = (NTT - l) & (NTT - 1);
-    const cx<T> zl = z[zrow(l) * C + c];
-    const cx<T> zm = conj(z[zrow(m) * C + c]);
+    const cx<T> zl = z[l * C + c];
+    const cx<T> zm = conj(z[m * C + c]);
     const cx<T> x1 = scale(add(zl, zm), T(0.5));
     const cx<T> x2 = scale(mul_mi(sub(zl, zm)), T(0.5));
     const T lk1 = lk1v[i], lk2 = lk2v[i];
@@ -619,8 +606,8 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2 * lk2, l1.y + pl.y * lk2 + ql.y * lk2 * lk2);
     const cx<T> y1 = cdiv(x1, s1);
     const cx<T> y2 = cdiv(x2, s2);
-    z[zrow(l) * C + c] = add(y1, mul_i(y2));
-    if (m != l) z[zrow(m) * C + c] = add(conj(y1), mul_i(conj(y2)));
+    z[l * C + c] = add(y1, mul_i(y2));
+    if (m != l) z[m * C + c] = add(conj(y1), mul_i(conj(y2)));
   }
   __syncthreads();
   fft_lds<T, NTT, C, C, NT, +1>(z, s_tw);
@@ -631,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       if (W2 % NT == 0 || w < W2) {
         const int j = w / C2, c = w - (w / C2) * C2;
         const T s = ta.aij[j];
-        const cx<T> a = scale(z[zrow(j) * C + 2 * c], s), b = scale(z[zrow(j) * C + 2 * c + 1], s);
+        const cx<T> a = scale(z[2 * w], s), b = scale(z[2 * w + 1], s);
         *reinterpret_cast<float4*>(S + j * ns + col0 + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
       }
     }
@@ -641,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W % NT == 0 || w < W) {
         const int j = w / C, c = w - (w / C) * C;
-        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[zrow(j) * C + c], ta.aij[j]);
+        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
       }
     }
   }
@@ -1078,21 +1065,9 @@ int rows_levels_per_block(int dim, int n) {
   return dim == 1 ? row_cfg<1, 8>::RB : 1;
 }
 
-// Block order of the forward row pass: level-pipelined per XCD (see
-// k_rows_fwd) unless PINT_ROWS_ORDER=linear.
-static int rows_xcd_order() {
-  static const int v = [] {
-    const char* s = std::getenv("PINT_ROWS_ORDER");
-    return (s && std::strcmp(s, "linear") == 0) ? 0 : 1;
-  }();
-  return v;
-}
-
 template <typename T, typename TO, int DIM, int N, bool WIDE, typename RT>
-static hipError_t launch_rows_fwd_w(const ResidArgs& a0, TO* S, double* rout, const DctTables<T>& dt, int nt,
+static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
-  ResidArgs a = a0;
-  a.xcd_order = rows_xcd_order();
   using C = row_fwd_cfg<DIM, N, WIDE>;
   const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
   if (mode == 0)

@@ -68,7 +68,6 @@ struct ResidArgs {
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
   int bcast;        // the iterate is u0 at every level (first iteration)
-  int xcd_order;    // level-pipelined block order per XCD (2D forward pass)
 };
 
 struct FinArgs {
