@@ -234,6 +234,28 @@ int pint_plan_alpha(const pint_plan* plan, double* alpha);
 int pint_solve(pint_plan* plan, const double* d_u0, double* d_U, void* d_work, size_t work_bytes,
                void* stream, pint_report* rep);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pint_solve
+ * with the library's own static device workspace instead of d_work.  It
+ * allocates nothing (no hipMalloc / hipFree, no allocating library call).
+ *   - Workspace: a file-scope device array of PINT_NOALLOC_WORKSPACE_BYTES
+ *     (64 MiB) that every device running the library holds until the process
+ *     ends; a problem whose pint_plan_workspace_size exceeds it returns
+ *     PINT_ENOMEM (e.g. FP64 up to 128^2 x 256, mixed up to 128^2 x 128).
+ *   - The plan is created beforehand with pint_plan_create (which does
+ *     allocate its small table block); d_u0 and d_U are as for pint_solve.
+ *   - PINT_FLAG_SOLVE_GRAPH and PINT_FLAG_STAGE_TIMING are rejected
+ *     (PINT_EINVAL): both create runtime objects.
+ *   - Every call on one device shares that device's workspace, so calls that
+ *     overlap on one GPU (other host threads or streams) race; serialize
+ *     them.  Nothing in the workspace needs to start at zero: the solve
+ *     initializes what it reads.
+ * Returns as pint_solve.
+ */
+#define PINT_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int pint_solve_noalloc(pint_plan* plan, const double* d_u0, double* d_U, void* stream, pint_report* rep);
+
 /* ---- stage entry points (same kernels as pint_solve; used for per-stage parity) ----
  * Working precision W: double for PINT_PREC_FP64, float otherwise (for
  * PINT_PREC_MIXED the forward transform inside pint_solve and

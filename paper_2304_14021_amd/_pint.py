@@ -32,7 +32,7 @@ HIST = 64
 EXPORTS = (
     "pint_status_string", "pint_last_error", "pint_version",
     "pint_plan_create", "pint_plan_destroy", "pint_plan_last_error", "pint_plan_workspace_size",
-    "pint_plan_alpha", "pint_solve", "pint_residual", "pint_dct", "pint_time_solve",
+    "pint_plan_alpha", "pint_solve", "pint_solve_noalloc", "pint_residual", "pint_dct", "pint_time_solve",
     "pint_precond_apply", "pint_diagnostics", "pint_time_eig",
     "pint_server_create", "pint_server_submit", "pint_server_submit_device", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
     "pint_server_destroy", "pint_server_last_error",
@@ -114,6 +114,7 @@ class Lib:
         d.pint_plan_workspace_size.argtypes = [vp, ct.POINTER(sz)]
         d.pint_plan_alpha.argtypes = [vp, ct.POINTER(dbl)]
         d.pint_solve.argtypes = [vp, vp, vp, vp, sz, vp, ct.POINTER(Report)]
+        d.pint_solve_noalloc.argtypes = [vp, vp, vp, vp, ct.POINTER(Report)]
         d.pint_residual.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         d.pint_dct.argtypes = [vp, vp, vp, i, vp]
         d.pint_time_solve.argtypes = [vp, vp, dbl, vp]

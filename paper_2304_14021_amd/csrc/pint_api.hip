@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1008,6 +1009,62 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
     set_err(&pl->err, status, status == PINT_ENOCONV ? "not converged within max_iter" : "iteration diverged");
   }
   return status;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ no-alloc solve
+// A file-scope device array serves as the workspace of pint_solve_noalloc.
+// Each device that loads the library holds its own copy until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host it
+// names a stand-in, not device memory): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[PINT_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr size_t kNoallocBytes = size_t(PINT_NOALLOC_WORKSPACE_BYTES);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_err(nullptr, PINT_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(nullptr, PINT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_err(nullptr, PINT_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PINT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pint_solve_noalloc(pint_plan* pl, const double* d_u0, double* d_U, void* stream, pint_report* rep) {
+  if (!pl) return set_err(nullptr, PINT_EINVAL, "plan is NULL");
+  if (pl->p.flags & (PINT_FLAG_SOLVE_GRAPH | PINT_FLAG_STAGE_TIMING))
+    return set_err(&pl->err, PINT_EINVAL,
+                   "pint_solve_noalloc takes no PINT_FLAG_SOLVE_GRAPH or PINT_FLAG_STAGE_TIMING (both create "
+                   "runtime objects)");
+  const size_t need = work_size(pl);
+  if (need > kNoallocBytes)
+    return set_err(&pl->err, PINT_ENOMEM,
+                   "problem needs " + std::to_string(need) + " bytes of workspace; the static workspace of "
+                   "pint_solve_noalloc holds " + std::to_string(kNoallocBytes));
+  void* work = nullptr;
+  const int rc = scratch_for_current_device(&work);
+  if (rc) {
+    pl->err = g_last_error;
+    return rc;
+  }
+  return pint_solve(pl, d_u0, d_U, work, kNoallocBytes, stream, rep);
 }
 
 int pint_residual(pint_plan* pl, const double* d_u0, const double* d_U, double* d_r, void* d_work,
