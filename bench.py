@@ -409,10 +409,10 @@ def main():
     # ~5% at this size, and solve graphs need a non-default stream
     side = torch.cuda.Stream(device=dev)
 
-    def run(prec, steps, warmup, timing, time_path="auto", alpha=None, graph=False, strict=True):
+    def run(prec, steps, warmup, timing, time_path="auto", alpha=None, graph=False, strict=True, field=False):
         q = p if alpha is None else dataclasses.replace(p, alpha=alpha)
         s = Solver.for_problem(q, precision=prec, device=dev, stage_timing=timing, time_path=time_path,
-                               graph=graph)
+                               graph=graph, field_jacobian=field)
         torch.cuda.synchronize()  # u0 and the workspace were made on the default stream
         with torch.cuda.stream(side):
             U = torch.empty(p.shape, dtype=torch.float64, device=dev)
@@ -527,6 +527,9 @@ def main():
         if head_alpha is not None and head_alpha != p.alpha:
             variants += [(args.precision, "fft", p.alpha)]
         variants += [("fp32_norefine", "fft", None)]  # the unrefined plateau (not at the 1e-10 bar)
+        if p.op == "ch":
+            # the space-varying averaged Jacobian (inner BiCGStab per outer step)
+            variants += [(args.precision, "field", head_alpha)]
         # BF16 runs take a larger alpha where admissible (alpha R^{N_t} < 1/2)
         # at 512^2 x 1024 the alpha part of the contraction, alpha R^{N_t} / (1 - alpha R^{N_t}) with
         # R^{N_t} ~ exp(T / (4 eps^2)) ~ 85, is 0.09 at alpha = 1e-3 and 0.5 at 4e-3 (which then does not
@@ -535,14 +538,16 @@ def main():
         variants += [("mixed", "dense", None), ("fp32", "dense", None), ("bf16x3", "dense", bf16_alpha),
                      ("bf16", "dense", bf16_alpha), ("bf16_norefine", "dense", bf16_alpha)]
         for prec, tp, al in variants:
-            key = prec if tp == "fft" else f"{prec}_dense"
+            key = prec if tp == "fft" else f"{prec}_{tp}"
             if prec == args.precision and tp == "fft":
                 key = f"{prec}_alpha_{al:g}"
-            elo, _, repso, Uo = run(prec, ps, pw, False, tp, al, strict=False)
+            field = tp == "field"
+            elo, _, repso, Uo = run(prec, ps, pw, False, "auto" if field else tp, al, strict=False, field=field)
             log(f"{key} status {repso[-1]['status']} update history {['%.1e' % x for x in repso[-1]['upd_hist']]}")
             Uoh = Uo.cpu().numpy()
             d = {"value": p.dof * ps / elo, "ms_per_step": elo / ps * 1e3, "steps": ps,
                  "status": repso[-1]["status"], "iterations": repso[-1]["iterations"], "alpha": repso[-1]["alpha"],
+                 **({"inner_iterations": repso[-1]["inner_iterations"]} if field else {}),
                  "rel_err_vs_oracle": golden_deviation(name, Uoh)["rel"],
                  "rel_diff_vs_headline": float(np.max(np.sqrt(np.sum((Uoh - Uh).reshape(p.nt, -1) ** 2, axis=1)))
                                                / np.max(np.sqrt(np.sum(Uh.reshape(p.nt, -1) ** 2, axis=1))))}

@@ -110,6 +110,26 @@ extern "C" {
                                             fill pint_report.mass_drift and
                                             energy_monotone (one more read of
                                             U and two small kernels)           */
+#define PINT_FLAG_FIELD_JACOBIAN   0x20u /* PINT_OP_CH: the quasi-Newton step uses
+                                            the averaged Jacobian as Section 4.1
+                                            defines it (eq. approx_jacobian),
+                                            J~ = diag((1/N_t) sum_n 3 u_n^2),
+                                            varying in space, so that Step-(2)
+                                            of eq. pintiter_CH is no longer
+                                            diagonal in the cosine basis; each
+                                            step solves G~'(U) delta = r(U) by
+                                            BiCGStab on the space-time vectors,
+                                            preconditioned by the scalar-c_bar
+                                            solve (inner residual reduced by
+                                            1e-3, at most 30 inner iterations;
+                                            pint_report.inner_iterations).  The
+                                            fixed point is unchanged.  Needs
+                                            8 more FP64 space-time vectors of
+                                            workspace; synchronizes with the
+                                            stream several times per inner
+                                            iteration; not with
+                                            PINT_FLAG_SOLVE_GRAPH or
+                                            PINT_FLAG_STAGE_TIMING             */
 
 #define PINT_HIST 64
 
@@ -177,7 +197,8 @@ typedef struct pint_report {
    *                (whose flow has no such energy) or when not computed.   */
   double mass_drift;
   int energy_monotone;
-  int reserved_;
+  int inner_iterations;        /* BiCGStab iterations over the whole solve
+                                  (PINT_FLAG_FIELD_JACOBIAN), else 0          */
 } pint_report;
 
 typedef struct pint_plan pint_plan;
@@ -286,6 +307,20 @@ int pint_time_solve(pint_plan* plan, void* d_S, double c_bar, void* stream);
  * working-precision DCT and time solve. */
 int pint_precond_apply(pint_plan* plan, const double* d_r, double* d_delta, double c_bar,
                        void* d_work, size_t work_bytes, void* stream);
+
+/* The inner solve of PINT_FLAG_FIELD_JACOBIAN as a stage: delta = G~'(U)^{-1} r
+ * with G~'(U) = C1^(alpha) (x) I - I (x) Lap_h J~(U) + I (x) Lap_h
+ * + eps^2 I (x) Lap_h^2 and J~(U) = diag((1/N_t) sum_n 3 u_n^2) (Section 4.1,
+ * eq. approx_jacobian), by BiCGStab preconditioned with the scalar-c_bar
+ * solve (c_bar the mean of J~) until the residual norm has dropped by
+ * inner_rtol or after inner_max iterations.  d_U, d_r, d_delta:
+ * [N_t][N_y][N_x] FP64 device arrays (d_r is not modified); d_u0 as for
+ * pint_solve (not read by the operator).  The plan must carry
+ * PINT_FLAG_FIELD_JACOBIAN; d_work as for pint_solve.  Synchronizes.
+ * *inner_iterations (nullable) receives the iterations taken. */
+int pint_field_jacobian_solve(pint_plan* plan, const double* d_u0, const double* d_U, const double* d_r,
+                              double* d_delta, double inner_rtol, int inner_max, void* d_work, size_t work_bytes,
+                              void* stream, int* inner_iterations);
 
 /* The FP64 eigendecomposition of the time-step pencil of a plan with
  * nonuniform steps (pint_problem.dts; Section 1): h_V [N_t][N_t] with the

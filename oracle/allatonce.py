@@ -221,6 +221,38 @@ def precond_matrix(p, c_bar: float = 0.0) -> sp.csr_matrix:
     return m.tocsr()
 
 
+def jacobian_field(U: np.ndarray) -> np.ndarray:
+    """The time-averaged Jacobian of the cubic term as the paper defines it
+    (eq. approx_jacobian): (1/N_t) sum_n J_s(u_n) with J_s(u) = diag(3 u^2), a
+    diagonal that still varies in space; returned as the field of its
+    diagonal entries (the shape of one level)."""
+    return np.mean(3.0 * U * U, axis=0)
+
+
+def precond_matrix_field(p, jfield: np.ndarray) -> sp.csr_matrix:
+    """The approximate Jacobian of eq. approx_jacobian (PinT-I) with the
+    space-varying averaged Jacobian J~ = diag(jfield):
+        C1^(a) (x) I - I (x) Lap_h J~ + I (x) Lap_h + eps^2 (I (x) Lap_h^2),
+    whose Step-(2) systems (eq. pintiter_CH) lam_{1,l} I - Lap_h J~ + Lap_h +
+    eps^2 Lap_h^2 are not diagonal in the cosine basis."""
+    if p.op != "ch":
+        raise ValueError("the space-varying averaged Jacobian is built for PinT-I")
+    lap = ops.laplacian(p.dim, p.n, p.h)
+    lap2 = (lap @ lap).tocsr()
+    k = (-(lap @ sp.diags(np.asarray(jfield, dtype=np.float64).reshape(-1))) + lap + p.eps ** 2 * lap2).tocsr()
+    c1, _ = circulant_blocks(p.nt, p.dt, 1.0, p.alpha)
+    eye_s = sp.identity(lap.shape[0], format="csr")
+    eye_t = sp.identity(p.nt, format="csr")
+    return (sp.kron(sp.csr_matrix(c1), eye_s) + sp.kron(eye_t, k)).tocsr()
+
+
+def precond_solve_field(p, r: np.ndarray, jfield: np.ndarray) -> np.ndarray:
+    """delta = G~'^{-1} r with the space-varying averaged Jacobian, by a sparse
+    direct solve (small sizes only)."""
+    m = precond_matrix_field(p, jfield).tocsc()
+    return spla.spsolve(m, r.reshape(-1)).reshape(r.shape)
+
+
 def precond_solve(p, r: np.ndarray, c_bar: float = 0.0) -> np.ndarray:
     """delta = P_alpha^{-1} r by a sparse direct (SuperLU) solve.  For small
     space-time sizes only."""

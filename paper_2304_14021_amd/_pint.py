@@ -26,6 +26,7 @@ FLAG_STAGE_TIMING = 0x2
 FLAG_BF16_SPLIT = 0x4
 FLAG_SOLVE_GRAPH = 0x8
 FLAG_INVARIANTS = 0x10
+FLAG_FIELD_JACOBIAN = 0x20
 HIST = 64
 
 # Every symbol include/pint.h declares (checked by the CPU test suite).
@@ -33,7 +34,7 @@ EXPORTS = (
     "pint_status_string", "pint_last_error", "pint_version",
     "pint_plan_create", "pint_plan_destroy", "pint_plan_last_error", "pint_plan_workspace_size",
     "pint_plan_alpha", "pint_solve", "pint_solve_noalloc", "pint_residual", "pint_dct", "pint_time_solve",
-    "pint_precond_apply", "pint_diagnostics", "pint_time_eig",
+    "pint_precond_apply", "pint_diagnostics", "pint_time_eig", "pint_field_jacobian_solve",
     "pint_server_create", "pint_server_submit", "pint_server_submit_device", "pint_server_wait", "pint_server_cancel", "pint_server_stats",
     "pint_server_destroy", "pint_server_last_error",
 )
@@ -60,7 +61,7 @@ class Report(ct.Structure):
         ("alpha_used", ct.c_double), ("c_bar", ct.c_double), ("est_rel_err", ct.c_double),
         ("res_hist", ct.c_double * HIST), ("upd_hist", ct.c_double * HIST),
         ("ms_stage", ct.c_double * 8), ("ms_total", ct.c_double),
-        ("mass_drift", ct.c_double), ("energy_monotone", ct.c_int), ("reserved_", ct.c_int),
+        ("mass_drift", ct.c_double), ("energy_monotone", ct.c_int), ("inner_iterations", ct.c_int),
     ]
 
 
@@ -121,6 +122,7 @@ class Lib:
         d.pint_precond_apply.argtypes = [vp, vp, vp, dbl, vp, sz, vp]
         d.pint_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         d.pint_time_eig.argtypes = [vp, vp, vp, vp]
+        d.pint_field_jacobian_solve.argtypes = [vp, vp, vp, vp, vp, dbl, i, vp, sz, vp, ct.POINTER(i)]
         d.pint_server_create.argtypes = [ct.POINTER(ServerConfig), ct.POINTER(vp)]
         d.pint_server_submit.argtypes = [vp, ct.POINTER(Problem), vp, ct.POINTER(ct.c_uint64)]
         d.pint_server_submit_device.argtypes = [vp, ct.POINTER(Problem), vp, vp, ct.POINTER(ct.c_uint64)]
@@ -238,6 +240,14 @@ class Plan:
         self.lib.check(self.lib.dll.pint_precond_apply(self.h, r_ptr, d_ptr, c_bar, work_ptr, work_bytes, stream),
                        self.h)
 
+    def field_jacobian_solve_raw(self, u0_ptr, U_ptr, r_ptr, d_ptr, inner_rtol, inner_max, work_ptr, work_bytes,
+                                 stream=0) -> int:
+        it = ct.c_int()
+        self.lib.check(self.lib.dll.pint_field_jacobian_solve(self.h, u0_ptr, U_ptr, r_ptr, d_ptr, inner_rtol,
+                                                              inner_max, work_ptr, work_bytes, stream,
+                                                              ct.byref(it)), self.h)
+        return it.value
+
     def time_eig(self):
         """(V, W, d) of the plan's FP64 time-step eigendecomposition (host arrays)."""
         import numpy as np
@@ -264,4 +274,5 @@ def report_dict(rep: Report) -> dict:
         "ms_total": rep.ms_total,
         "mass_drift": rep.mass_drift,
         "energy_monotone": rep.energy_monotone,
+        "inner_iterations": rep.inner_iterations,
     }

@@ -24,6 +24,7 @@
 #include "pint_kernels.hpp"
 #include "fft_lds.hpp"
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -34,6 +35,12 @@ thread_local hipEvent_t g_launch_ev0 = nullptr, g_launch_ev1 = nullptr;
 
 // Neumann (ghost-reflection) index clamp.
 __device__ __forceinline__ int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
+
+// Value at offset off of the predecessor of the first level: the datum u0,
+// or wrap_alpha u_{N_t} for the alpha-circulant operator.
+__device__ __forceinline__ double prev0(const ResidArgs& a, int off, size_t ns) {
+  return a.wrap ? a.wrap_alpha * a.U[size_t(a.nt - 1) * ns + off] : a.u0[off];
+}
 
 template <typename T>
 __device__ __forceinline__ T& comp(cx<T>& c, int i) {
@@ -82,14 +89,16 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
   constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
-  constexpr int R0 = VB > ZB ? VB : ZB;
+  constexpr int R0 = VB > ZB ? (VB > GB ? VB : GB) : (ZB > GB ? ZB : GB);
   constexpr int NV = DIM == 2 ? 1 : RB;
-  constexpr int RED = NT * NV * 8;  // reduction scratch, reuses the G region
-  __shared__ __align__(16) unsigned char lds[R0 + (GB > RED ? GB : RED)];
+  // one buffer holds v, then g, then the packed DCT input (each phase keeps
+  // its results in registers across the barrier before overwriting it)
+  __shared__ __align__(16) unsigned char lds[R0];
+  __shared__ double red[NT * NV];
   __shared__ cx<T> s_tw[N], s_wq[N];
   RT* V = reinterpret_cast<RT*>(lds);
   cx<T>* z = reinterpret_cast<cx<T>*>(lds);
-  RT* G = reinterpret_cast<RT*>(lds + R0);
+  RT* G = reinterpret_cast<RT*>(lds);
   if (MODE == 0) {
     table_to_lds<T, NT, N>(s_tw, dt.tw);
     table_to_lds<T, NT, N>(s_wq, dt.wq);
@@ -124,7 +133,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
         } else {
           hn[i] = a.U[lev * ns + off];
           // v = theta u_n + (1 - theta) u_{n-1}: no u_{n-1} halo for theta = 1
-          if (omth != 0.0) hm[i] = lev == 0 ? a.u0[off] : a.U[(lev - 1) * ns + off];
+          if (omth != 0.0) hm[i] = lev == 0 ? prev0(a, off, ns) : a.U[(lev - 1) * ns + off];
         }
       }
     }
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
           on[i] = om[i] = a.u0[off];
         } else {
           on[i] = a.U[n * ns + off];
-          om[i] = n == 0 ? a.u0[off] : a.U[(n - 1) * ns + off];
+          om[i] = n == 0 ? prev0(a, off, ns) : a.U[(n - 1) * ns + off];
         }
       }
     }
@@ -161,8 +170,14 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     }
   }
   __syncthreads();
-  // Phase 2: g at positions clamp(y0-1 .. y0+RB) -> G.
-  for (int idx = tid; idx < GR * N; idx += NT) {
+  // Phase 2: g at positions clamp(y0-1 .. y0+RB) -> registers -> G.
+  constexpr int GW = GR * N, ITG = cdiv_i(GW, NT);
+  RT gval[ITG];
+#pragma unroll
+  for (int i = 0; i < ITG; ++i) {
+    const int idx = tid + i * NT;
+    gval[i] = RT(0);
+    if (!(GW % NT == 0 || idx < GW)) continue;
     const int gr = idx / N, x = idx - (idx / N) * N;
     int c, yg = 0;
     if (DIM == 2) {
@@ -174,23 +189,33 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     const RT v = V[c * N + x];
     RT lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - RT(2) * v;
     if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - RT(2) * v;
-    RT g = RT(a.c3) * v * v * v + RT(a.c1) * v + RT(a.c2) * (lap * RT(a.inv_h2));
+    const int goff = DIM == 2 ? yg * N + x : x;
+    // cubic term, or the averaged Jacobian field times v (linearized operator)
+    const RT nl = a.jfield ? RT(a.jfield[goff]) * v : RT(a.c3) * v * v * v;
+    RT g = nl + RT(a.c1) * v + RT(a.c2) * (lap * RT(a.inv_h2));
     if (a.c1p != 0.0) {
       const int n = DIM == 2 ? lev : lev + gr;
-      const int off = DIM == 2 ? yg * N + x : x;
-      const RT um = RT((bc || n == 0) ? a.u0[off] : a.U[(n - 1) * ns + off]);
+      const RT um = RT(bc ? a.u0[goff] : (n == 0 ? prev0(a, goff, ns) : a.U[(n - 1) * ns + goff]));
       g += RT(a.c1p) * um;
     }
-    G[idx] = g;
+    gval[i] = g;
+  }
+  __syncthreads();  // every v read
+#pragma unroll
+  for (int i = 0; i < ITG; ++i) {
+    const int idx = tid + i * NT;
+    if (GW % NT == 0 || idx < GW) G[idx] = gval[i];
   }
   __syncthreads();
-  // Phase 3: r on the own rows; packed into z (overlays V, which is dead).
+  // Phase 3: r on the own rows -> registers -> packed into z (same buffer).
   double rsq[NV];
+  RT rval[ITO];
 #pragma unroll
   for (int q = 0; q < NV; ++q) rsq[q] = 0.0;
 #pragma unroll
   for (int i = 0; i < ITO; ++i) {
     const int w = tid + i * NT;
+    rval[i] = RT(0);
     if (!(OW % NT == 0 || w < OW)) continue;
     const int rr = w / N, x = w - (w / N) * N;
     const int gc = DIM == 2 ? rr + 1 : rr;
@@ -202,12 +227,20 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
 #pragma unroll
     for (int qq = 0; qq < NV; ++qq)
       if (DIM == 2 || qq == rr) rsq[qq] += double(r) * double(r);
+    rval[i] = r;
+  }
+  __syncthreads();  // every g read
+#pragma unroll
+  for (int i = 0; i < ITO; ++i) {
+    const int w = tid + i * NT;
+    if (!(OW % NT == 0 || w < OW)) continue;
+    const int rr = w / N, x = w - (w / N) * N;
     if (MODE == 1) {
       const int n = DIM == 2 ? lev : lev + rr;
       const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-      rout[n * ns + off] = double(r);
+      rout[n * ns + off] = double(rval[i]);
     } else {
-      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(r);
+      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(rval[i]);
     }
   }
   __syncthreads();
@@ -229,11 +262,11 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
       }
     }
   }
-  // Partial sums of r^2 (G is free scratch now).
+  // Partial sums of r^2.
   bool ismax[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) ismax[q] = false;
-  block_reduce<NT, NV>(reinterpret_cast<double*>(G), rsq, ismax);
+  block_reduce<NT, NV>(red, rsq, ismax);
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -887,6 +920,7 @@ __global__ __launch_bounds__(256) void k_init_ctrl(Ctrl* c, Ctrl* host, InitArgs
     host->iter = 0;
     host->done = 0;
     host->status = PINT_ENOCONV;
+    host->c_bar = c->c_bar;
   }
 }
 
@@ -996,6 +1030,79 @@ __global__ __launch_bounds__(256) void k_invariants_fin(const double* __restrict
   }
 }
 
+// ------------------------------------------- space-varying averaged Jacobian
+// j(x) = (1/N_t) sum_n 3 u_n(x)^2 (eq. approx_jacobian): one thread per point,
+// levels summed in order.
+__global__ __launch_bounds__(256) void k_jfield(const double* __restrict__ U, double* __restrict__ j, int nt,
+                                                 int ns) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ns) return;
+  double s = 0.0;
+  for (int n = 0; n < nt; ++n) {
+    const double u = U[size_t(n) * ns + i];
+    s += 3.0 * u * u;
+  }
+  j[i] = s / nt;
+}
+
+__global__ __launch_bounds__(256) void k_axpbypcz(double* __restrict__ out, double a, const double* __restrict__ x,
+                                                   double b, const double* __restrict__ y, double c,
+                                                   const double* __restrict__ z, size_t n) {
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
+    double v = a * x[i] + b * y[i];
+    if (z) v += c * z[i];
+    out[i] = v;
+  }
+}
+
+// Fixed-order partial dot products: block b sums i = b*256 + t + k*DOT_BLOCKS*256.
+struct DotPtrs {
+  const double* x[4];
+  const double* y[4];
+};
+__global__ __launch_bounds__(256) void k_dots(DotPtrs d, int pairs, size_t n, double* __restrict__ partial) {
+  __shared__ double red[4 * 4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < n; i += size_t(DOT_BLOCKS) * 256)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < pairs) v[q] += d.x[q][i] * d.y[q][i];
+  const bool ismax[4] = {false, false, false, false};
+  block_reduce_waves<256, 4>(red, v, ismax);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < pairs; ++q) partial[size_t(q) * DOT_BLOCKS + blockIdx.x] = v[q];
+}
+
+// U = base + delta for block (level n, share b of nbl); partials as k_rows_inv.
+__global__ __launch_bounds__(256) void k_update_plain(double* __restrict__ U, const double* __restrict__ u0,
+                                                       const double* __restrict__ delta, double* __restrict__ part,
+                                                       int ns, int nbl, int bcast) {
+  __shared__ double red[4 * 4];
+  const int n = blockIdx.x / nbl, b = blockIdx.x - (blockIdx.x / nbl) * nbl;
+  const int chunk = ns / nbl;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = b * chunk + threadIdx.x; i < (b + 1) * chunk; i += 256) {
+    const size_t gi = size_t(n) * ns + i;
+    const double del = delta[gi];
+    const double u = (bcast ? u0[i] : U[gi]) + del;
+    U[gi] = u;
+    acc[0] += del * del;
+    acc[1] += u * u;
+    acc[2] += 3.0 * u * u;
+    const double ad = del < 0 ? -del : del;
+    acc[3] = (ad != ad || ad > acc[3]) ? ad : acc[3];
+  }
+  const bool ismax[4] = {false, false, false, true};
+  block_reduce_waves<256, 4>(red, acc, ismax);
+  if (threadIdx.x == 0) {
+    double* pp = part + size_t(blockIdx.x) * PART_STRIDE;
+    pp[PART_DSQ] = acc[0];
+    pp[PART_USQ] = acc[1];
+    pp[PART_U2] = acc[2];
+    pp[PART_DMAX] = acc[3];
+  }
+}
+
 // ============================================================== launchers
 #define PINT_CHECK_LAUNCH()            \
   do {                                 \
@@ -1011,13 +1118,14 @@ struct row_cfg {
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
-// The forward pass holds v (RB + 4 rows), g (RB + 2 rows) and the FFT buffer
-// in LDS, FP64: for N >= 256 it takes half the rows of the inverse pass so
-// that two to three blocks fit per CU and their phases overlap (measured:
-// -35% at 256^2; at 128^2 the taller block is as fast).
+// The forward pass holds v (RB + 4 rows), then g, then the FFT input in one
+// LDS buffer (FP64 for v and g): 48 KB for 8 rows of 512, so two blocks fit
+// per CU.
 template <int DIM, int N, bool WIDE>
 struct row_fwd_cfg {
-  static constexpr int RB = (DIM == 2 && N >= 256 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
+  // 256^2: half the inverse pass's height (8 rows; 16 measured slower); 512^2:
+  // the full 8 rows (4 rows: 1171 us per launch at 512^2 x 1024, 8 rows: 1118 us)
+  static constexpr int RB = (DIM == 2 && N == 256 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
   // 2D N <= 128: 512 threads per block shorten each thread's serial chain
   static constexpr int NT0 = (DIM == 2 && N >= 64) ? 512 : 256;
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
@@ -1295,6 +1403,41 @@ hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool 
     PINT_CHECK_LAUNCH();
   }
   PINT_LAUNCH(k_init_ctrl, dim3(1), dim3(256), 0, st, c, host, a, dof, nparts);
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_jfield(const double* U, double* j, int nt, int ns, hipStream_t st) {
+  PINT_LAUNCH(k_jfield, dim3((ns + 255) / 256), dim3(256), 0, st, U, j, nt, ns);
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, const double* y, double c,
+                           const double* z, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  PINT_LAUNCH(k_axpbypcz, dim3(unsigned(blocks)), dim3(256), 0, st, out, a, x, b, y, c, z, n);
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_dots(const double* const* xs, const double* const* ys, int pairs, size_t n, double* partial,
+                       hipStream_t st) {
+  if (pairs < 1 || pairs > 4) return hipErrorInvalidValue;
+  DotPtrs d{};
+  for (int q = 0; q < pairs; ++q) {
+    d.x[q] = xs[q];
+    d.y[q] = ys[q];
+  }
+  PINT_LAUNCH(k_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, d, pairs, n, partial);
+  PINT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_update_plain(double* U, const double* u0, const double* delta, double* part, int nt, int ns,
+                               int nbl, int bcast, hipStream_t st) {
+  if (ns % nbl != 0) return hipErrorInvalidValue;
+  PINT_LAUNCH(k_update_plain, dim3(nt * nbl), dim3(256), 0, st, U, u0, delta, part, ns, nbl, bcast);
   PINT_CHECK_LAUNCH();
   return hipSuccess;
 }

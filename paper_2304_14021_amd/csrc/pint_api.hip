@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <new>
 #include <string>
@@ -204,6 +205,14 @@ int validate(const pint_problem* p, std::string* err) {
     if (nb == 0 || ns % nb != 0)
       return set_err(err, PINT_EINVAL, "the dense time contraction needs N_t >= 32 and N_s a multiple of " +
                                            std::to_string(nb ? nb : 32));
+  }
+  if (p->flags & PINT_FLAG_FIELD_JACOBIAN) {
+    if (p->op != PINT_OP_CH)
+      return set_err(err, PINT_EINVAL, "the space-varying averaged Jacobian is for the PinT-I CH operator");
+    if (p->precision == PINT_PREC_FP32_NOREFINE || p->precision == PINT_PREC_BF16_NOREFINE)
+      return set_err(err, PINT_EINVAL, "the space-varying averaged Jacobian needs a refined precision");
+    if (p->flags & (PINT_FLAG_SOLVE_GRAPH | PINT_FLAG_STAGE_TIMING))
+      return set_err(err, PINT_EINVAL, "the space-varying averaged Jacobian takes no solve graph or stage timing");
   }
   if (p->max_iter < 0 || p->max_iter > PINT_HIST) return set_err(err, PINT_EINVAL, "max_iter must be in [0, 64]");
   if (p->rtol < 0.0) return set_err(err, PINT_EINVAL, "rtol must be >= 0");
@@ -471,8 +480,18 @@ size_t s64_bytes(const pint_plan* pl) { return pl->mixed ? align256((size_t)pl->
 size_t fin_bytes(const pint_plan* pl) {
   return align256(size_t(std::max(1, finalize_groups(pl->nt, pl->nbl, pl->nbl_f))) * 4 * sizeof(double));
 }
+// Inner solve of the space-varying averaged Jacobian (PINT_FLAG_FIELD_JACOBIAN):
+// eight FP64 space-time vectors, the field, dot-product partials and the
+// operator's own residual partials.
+constexpr int FIELD_VECS = 8;
+bool field_mode(const pint_plan* pl) { return (pl->p.flags & PINT_FLAG_FIELD_JACOBIAN) != 0; }
+size_t field_bytes(const pint_plan* pl) {
+  if (!field_mode(pl)) return 0;
+  return FIELD_VECS * align256(size_t(pl->nt) * pl->ns * 8) + align256(size_t(pl->ns) * 8) +
+         align256(size_t(4) * DOT_BLOCKS * 8) + part_bytes(pl);
+}
 size_t work_size(const pint_plan* pl) {
-  return s_bytes(pl) + s64_bytes(pl) + part_bytes(pl) + fin_bytes(pl) + align256(sizeof(Ctrl));
+  return s_bytes(pl) + s64_bytes(pl) + part_bytes(pl) + fin_bytes(pl) + align256(sizeof(Ctrl)) + field_bytes(pl);
 }
 
 int carve(pint_plan* pl, void* d_work, size_t bytes, Work& w) {
@@ -599,6 +618,185 @@ int begin_solve(pint_plan* pl, const double* d_u0, double* d_U, const Work& w, h
   return PINT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Outer iteration with the space-varying averaged Jacobian (eq. approx_jacobian,
+// PinT-I): U <- U + G~'(U)^{-1} r(U), with
+//   G~'(U) = C1^(alpha) (x) I - I (x) Lap_h J~ + I (x) Lap_h + eps^2 I (x) Lap_h^2,
+//   J~ = diag((1/N_t) sum_n 3 u_n^2),
+// whose Step-(2) systems are not diagonal in the cosine basis.  The linear
+// system is solved by BiCGStab on the space-time vectors, right-
+// preconditioned by the scalar-c_bar solve (the plan's own preconditioner:
+// DCT, alpha-circulant time solve, inverse DCT), until the inner residual has
+// dropped by FIELD_INNER_RTOL or FIELD_INNER_MAX iterations.  The operator is
+// applied in physical space by the residual kernel with the field in place
+// of the cubic term and the alpha corner in place of u0.  Every scalar of the
+// iteration comes from fixed-order reductions, so the solve is deterministic.
+constexpr double FIELD_INNER_RTOL = 1e-3;
+constexpr int FIELD_INNER_MAX = 30;
+
+struct FieldWork {
+  double* v[FIELD_VECS];  // R, X, Rh, P, Vn, Tn, Ph, Sh
+  double* jfield;
+  double* dots;           // [4][DOT_BLOCKS]
+  double* apart;          // partials of the operator applications
+};
+
+int field_carve(pint_plan* pl, void* d_work, FieldWork& f) {
+  unsigned char* b = static_cast<unsigned char*>(d_work) + (work_size(pl) - field_bytes(pl));
+  const size_t vb = align256(size_t(pl->nt) * pl->ns * 8);
+  for (int i = 0; i < FIELD_VECS; ++i, b += vb) f.v[i] = reinterpret_cast<double*>(b);
+  f.jfield = reinterpret_cast<double*>(b);
+  b += align256(size_t(pl->ns) * 8);
+  f.dots = reinterpret_cast<double*>(b);
+  b += align256(size_t(4) * DOT_BLOCKS * 8);
+  f.apart = reinterpret_cast<double*>(b);
+  return PINT_OK;
+}
+
+// Pinned host buffer for the dot-product partials of one solve.
+struct PinnedDots {
+  double* p = nullptr;
+  ~PinnedDots() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Solve G~'(U) X = R (R is overwritten) with the field f.jfield of U already
+// computed; cbar is the scalar averaged Jacobian of the preconditioner.
+int field_inner_solve(pint_plan* pl, const double* d_u0, FieldWork& f, double* R, double* X, double cbar,
+                      double rtol, int maxit, void* d_work, size_t work_bytes, hipStream_t st, double* hdots,
+                      int* iters) {
+  double *Rh = f.v[2], *P = f.v[3], *Vn = f.v[4], *Tn = f.v[5], *Ph = f.v[6], *Sh = f.v[7];
+  const size_t n = size_t(pl->nt) * pl->ns;
+  int rc = PINT_OK;
+  auto dots = [&](std::initializer_list<std::pair<const double*, const double*>> prs, double* out) -> int {
+    const double* xs[4];
+    const double* ys[4];
+    int q = 0;
+    for (auto& pr : prs) {
+      xs[q] = pr.first;
+      ys[q] = pr.second;
+      ++q;
+    }
+    HIPCHK(launch_dots(xs, ys, q, n, f.dots, st), "dot kernel");
+    HIPCHK(hipMemcpyAsync(hdots, f.dots, size_t(q) * DOT_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, st),
+           "dot copy");
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (int k = 0; k < q; ++k) {
+      double acc = 0.0;
+      for (int b = 0; b < DOT_BLOCKS; ++b) acc += hdots[size_t(k) * DOT_BLOCKS + b];
+      out[k] = acc;
+    }
+    return PINT_OK;
+  };
+  // out = -G~' v (the residual kernel with b = 0)
+  auto apply_neg = [&](const double* v, double* out) -> int {
+    ResidArgs ra = pl->ra;
+    ra.u0 = d_u0;  // not read: the first level's predecessor is the alpha corner
+    ra.U = v;
+    ra.part = f.apart;
+    ra.done = nullptr;
+    ra.bcast = 0;
+    ra.jfield = f.jfield;
+    ra.wrap = 1;
+    ra.nt = pl->nt;
+    ra.wrap_alpha = pl->alpha;
+    HIPCHK((launch_rows_fwd<double, double, double>(pl->dim, pl->n, ra, nullptr, out, pl->dtd, pl->nt, 1, st)),
+           "operator kernel");
+    return PINT_OK;
+  };
+  auto axpy = [&](double* out, double a, const double* x, double b, const double* y, double c,
+                  const double* z) -> int {
+    HIPCHK(launch_axpbypcz(out, a, x, b, y, c, z, n, st), "vector kernel");
+    return PINT_OK;
+  };
+  auto M = [&](const double* in, double* out) {
+    return pint_precond_apply(pl, in, out, cbar, d_work, work_bytes, st);
+  };
+  *iters = 0;
+  double d2[4];
+  if ((rc = dots({{R, R}}, d2))) return rc;
+  const double bnorm = std::sqrt(d2[0]);
+  if ((rc = M(R, X))) return rc;                       // x0 = M r (the scalar-c_bar step)
+  if ((rc = apply_neg(X, Tn))) return rc;              // r0 = r - A x0 = r + Tn
+  if ((rc = axpy(R, 1.0, R, 1.0, Tn, 0.0, nullptr))) return rc;
+  if ((rc = axpy(Rh, 1.0, R, 0.0, R, 0.0, nullptr))) return rc;
+  HIPCHK(hipMemsetAsync(P, 0, n * sizeof(double), st), "hipMemsetAsync");
+  HIPCHK(hipMemsetAsync(Vn, 0, n * sizeof(double), st), "hipMemsetAsync");
+  double rho = 1.0, alpha = 1.0, omega = 1.0;
+  if ((rc = dots({{Rh, R}, {R, R}}, d2))) return rc;
+  double rho_new = d2[0], rnorm = std::sqrt(d2[1]);
+  for (int in = 0; in < maxit && rnorm > rtol * bnorm && rho_new != 0.0; ++in) {
+    ++*iters;
+    const double beta = (rho_new / rho) * (alpha / omega);
+    // p = r + beta (p - omega v), with v = -Vn
+    if ((rc = axpy(P, 1.0, R, beta, P, beta * omega, Vn))) return rc;
+    if ((rc = M(P, Ph))) return rc;
+    if ((rc = apply_neg(Ph, Vn))) return rc;           // v = A ph = -Vn
+    if ((rc = dots({{Rh, Vn}}, d2))) return rc;
+    alpha = -rho_new / d2[0];
+    if ((rc = axpy(R, 1.0, R, alpha, Vn, 0.0, nullptr))) return rc;  // s = r - alpha v (in R)
+    if ((rc = M(R, Sh))) return rc;
+    if ((rc = apply_neg(Sh, Tn))) return rc;           // t = A sh = -Tn
+    if ((rc = dots({{Tn, R}, {Tn, Tn}}, d2))) return rc;
+    omega = d2[1] > 0.0 ? -d2[0] / d2[1] : 0.0;        // (t, s) / (t, t)
+    if ((rc = axpy(X, 1.0, X, alpha, Ph, omega, Sh))) return rc;
+    if ((rc = axpy(R, 1.0, R, omega, Tn, 0.0, nullptr))) return rc;  // r = s - omega t
+    rho = rho_new;
+    if ((rc = dots({{Rh, R}, {R, R}}, d2))) return rc;
+    rho_new = d2[0];
+    rnorm = std::sqrt(d2[1]);
+    if (omega == 0.0) break;
+  }
+  return PINT_OK;
+}
+
+int solve_field(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, size_t work_bytes, const Work& w,
+                hipStream_t st, int* inner_total) {
+  FieldWork f;
+  field_carve(pl, d_work, f);
+  double *R = f.v[0], *X = f.v[1];
+  const size_t n = size_t(pl->nt) * pl->ns;
+  PinnedDots hd;
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hd.p), 4 * DOT_BLOCKS * sizeof(double), hipHostMallocDefault),
+         "hipHostMalloc(dot partials)");
+  const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
+  if (bcast) {
+    HIPCHK(hipMemsetAsync(X, 0, n * sizeof(double), st), "hipMemsetAsync");
+    HIPCHK(launch_update_plain(d_U, d_u0, X, w.part, pl->nt, pl->ns, pl->nbl, 1, st), "broadcast");
+  }
+  InitArgs ia{d_u0, d_U, w.part, pl->nt, pl->ns, pl->nbl, 0};
+  HIPCHK(launch_init(ia, w.ctrl, pl->h_ctrl, pl->dof, true, st), "init kernels");
+  FinArgs fa{w.ctrl, pl->h_ctrl, w.part, w.fin, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, 0, pl->dof, pl->rtol,
+             pl->safety};
+  *inner_total = 0;
+  for (int it = 0; it < pl->max_iter; ++it) {
+    // outer residual r(U) (FP64, alpha = 0) and the field of U
+    ResidArgs ra = pl->ra;
+    ra.u0 = d_u0;
+    ra.U = d_U;
+    ra.part = w.part;
+    ra.done = nullptr;
+    ra.bcast = 0;
+    HIPCHK((launch_rows_fwd<double, double, double>(pl->dim, pl->n, ra, nullptr, R, pl->dtd, pl->nt, 1, st)),
+           "residual kernel");
+    HIPCHK(launch_jfield(d_U, f.jfield, pl->nt, pl->ns, st), "field kernel");
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const double cbar = reinterpret_cast<volatile double&>(pl->h_ctrl->c_bar);
+    int iters = 0;
+    const int rc = field_inner_solve(pl, d_u0, f, R, X, cbar, FIELD_INNER_RTOL, FIELD_INNER_MAX, d_work, work_bytes,
+                                     st, hd.p, &iters);
+    if (rc) return rc;
+    *inner_total += iters;
+    // U += delta, partials, control (stop rule, next c_bar)
+    HIPCHK(launch_update_plain(d_U, d_u0, X, w.part, pl->nt, pl->ns, pl->nbl, 0, st), "update kernel");
+    HIPCHK(launch_finalize(fa, st), "control kernel");
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (reinterpret_cast<volatile int&>(pl->h_ctrl->done)) break;
+  }
+  return PINT_OK;
+}
+
 void fill_report(const pint_plan* pl, const Ctrl& c, int status, pint_report* rep) {
   std::memset(reinterpret_cast<char*>(rep) + sizeof(size_t), 0, sizeof(pint_report) - sizeof(size_t));
   rep->status = status;
@@ -612,6 +810,7 @@ void fill_report(const pint_plan* pl, const Ctrl& c, int status, pint_report* re
   }
   rep->mass_drift = std::nan("");
   rep->energy_monotone = -1;
+  rep->inner_iterations = 0;
 }
 
 }  // namespace
@@ -919,6 +1118,21 @@ int pint_solve(pint_plan* pl, const double* d_u0, double* d_U, void* d_work, siz
       pl->ev.push_back(e);
     }
   }
+  if (field_mode(pl)) {
+    int inner = 0;
+    rc = solve_field(pl, d_u0, d_U, d_work, work_bytes, w, st, &inner);
+    if (rc) return rc;
+    const Ctrl& c = *pl->h_ctrl;
+    const int status = c.done ? c.status : PINT_ENOCONV;
+    if (rep) {
+      fill_report(pl, c, status, rep);
+      rep->inner_iterations = inner;
+      rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != PINT_OK)
+      set_err(&pl->err, status, status == PINT_ENOCONV ? "not converged within max_iter" : "iteration diverged");
+    return status;
+  }
   const bool bcast = (pl->p.flags & PINT_FLAG_INIT_BROADCAST_U0) != 0;
   // Enqueue as many iterations as the previous solve of this plan needed
   // (kernels after the device stop flag is set return at once), then check
@@ -1160,6 +1374,37 @@ int pint_precond_apply(pint_plan* pl, const double* d_r, double* d_delta, double
     HIPCHK(launch_rows_inv<float>(pl->dim, pl->n, ua, S, d_delta, pl->dtf, pl->nt, 1, st), "inverse x-dct");
   }
   return PINT_OK;
+}
+
+int pint_field_jacobian_solve(pint_plan* pl, const double* d_u0, const double* d_U, const double* d_r,
+                              double* d_delta, double inner_rtol, int inner_max, void* d_work, size_t work_bytes,
+                              void* stream, int* inner_iterations) {
+  if (!pl || !d_u0 || !d_U || !d_r || !d_delta) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  if (!field_mode(pl)) return set_err(&pl->err, PINT_EINVAL, "the plan lacks PINT_FLAG_FIELD_JACOBIAN");
+  if (!(inner_rtol > 0.0) || inner_max < 1) return set_err(&pl->err, PINT_EINVAL, "inner_rtol > 0, inner_max >= 1");
+  Work w;
+  int rc = carve(pl, d_work, work_bytes, w);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  FieldWork f;
+  field_carve(pl, d_work, f);
+  const size_t n = size_t(pl->nt) * pl->ns;
+  HIPCHK(launch_jfield(d_U, f.jfield, pl->nt, pl->ns, st), "field kernel");
+  std::vector<double> j(pl->ns);
+  HIPCHK(hipMemcpyAsync(j.data(), f.jfield, j.size() * sizeof(double), hipMemcpyDeviceToHost, st), "field copy");
+  HIPCHK(hipMemcpyAsync(f.v[0], d_r, n * sizeof(double), hipMemcpyDeviceToDevice, st), "residual copy");
+  HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+  double cbar = 0.0;
+  for (double x : j) cbar += x;
+  cbar /= double(pl->ns);
+  PinnedDots hd;
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hd.p), 4 * DOT_BLOCKS * sizeof(double), hipHostMallocDefault),
+         "hipHostMalloc(dot partials)");
+  int iters = 0;
+  rc = field_inner_solve(pl, d_u0, f, f.v[0], d_delta, cbar, inner_rtol, inner_max, d_work, work_bytes, st, hd.p,
+                         &iters);
+  if (inner_iterations) *inner_iterations = iters;
+  return rc;
 }
 
 int pint_time_eig(pint_plan* pl, double* h_V, double* h_W, double* h_d) {

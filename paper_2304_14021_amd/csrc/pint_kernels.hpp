@@ -68,6 +68,13 @@ struct ResidArgs {
   double inv_dt, inv_h2, theta;
   double c1, c1p, c2, c3;
   int bcast;        // the iterate is u0 at every level (first iteration)
+  // Linearized operator (approximate Jacobian of eq. approx_jacobian): with
+  // jfield non-null the cubic term c3 v^3 becomes jfield(x) v, and with wrap
+  // the predecessor of level 1 is wrap_alpha u_{N_t} (the alpha-circulant
+  // corner) instead of u0.
+  const double* jfield;
+  int wrap, nt;
+  double wrap_alpha;
 };
 
 struct FinArgs {
@@ -208,6 +215,20 @@ int finalize_groups(int nt, int nbl, int nbl_f);
 // reduction use a.part (nparts <= ceil(total / 4096) slots).
 hipError_t launch_init(const InitArgs& a, Ctrl* c, Ctrl* host, double dof, bool need_cbar, hipStream_t st);
 hipError_t launch_diagnostics(const DiagArgs& a, int nt, hipStream_t st);
+// Space-varying averaged Jacobian field j(x) = (1/N_t) sum_n 3 u_n(x)^2.
+hipError_t launch_jfield(const double* U, double* j, int nt, int ns, hipStream_t st);
+// out = a x + b y + c z (z may be null), n values.
+hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, const double* y, double c,
+                           const double* z, size_t n, hipStream_t st);
+// Partial sums of x_i y_i for `pairs` pairs in fixed-order blocks:
+// partial[q * DOT_BLOCKS + block].
+constexpr int DOT_BLOCKS = 512;
+hipError_t launch_dots(const double* const* xs, const double* const* ys, int pairs, size_t n, double* partial,
+                       hipStream_t st);
+// U = (bcast ? u0 : U) + delta level by level, with the update partials of
+// [level][block] (block = a 1/nbl share of the level) for the control kernel.
+hipError_t launch_update_plain(double* U, const double* u0, const double* delta, double* part, int nt, int ns,
+                               int nbl, int bcast, hipStream_t st);
 // Mass drift and energy monotonicity of u_0, u_1..u_{N_t} into the control
 // record and its host mirror; `scratch` holds 3 (N_t + 1) doubles.
 hipError_t launch_invariants(const DiagArgs& a, const double* u0, double* scratch, int nt, bool energy, Ctrl* c,

@@ -27,7 +27,8 @@ class Solver:
     def __init__(self, op: str, dim: int, n: int, nt: int, dt: float, theta: float = 1.0, eps: float = 1.0,
                  beta: float = 0.0, alpha: float = 1e-3, precision: str = "fp32", time_path: str = "auto",
                  rtol: float = 1e-10, max_iter: int = 30, broadcast_u0: bool = True, stage_timing: bool = False,
-                 graph: bool = False, invariants: bool = False, dts=None, device=None):
+                 graph: bool = False, invariants: bool = False, dts=None, field_jacobian: bool = False,
+                 device=None):
         _require_gpu()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         flags = (_pint.FLAG_INIT_BROADCAST_U0 if broadcast_u0 else 0) | (_pint.FLAG_STAGE_TIMING if stage_timing else 0)
@@ -36,6 +37,8 @@ class Solver:
         flags |= _pint.FLAG_SOLVE_GRAPH if graph else 0
         # invariants: the report carries the mass drift and energy monotonicity
         flags |= _pint.FLAG_INVARIANTS if invariants else 0
+        # field_jacobian: the space-varying averaged Jacobian with an inner Krylov solve (CH only)
+        flags |= _pint.FLAG_FIELD_JACOBIAN if field_jacobian else 0
         self.shape = (nt,) + (n,) * dim
         self.slice_shape = (n,) * dim
         self.dof = nt * n ** dim
@@ -113,6 +116,18 @@ class Solver:
         self.plan.precond_raw(r.data_ptr(), d.data_ptr(), c_bar, self._work_ptr(), self.plan.work_bytes,
                               self._stream())
         return d
+
+    def field_jacobian_solve(self, u0: torch.Tensor, U: torch.Tensor, r: torch.Tensor, inner_rtol: float = 1e-12,
+                             inner_max: int = 60):
+        """(delta, inner iterations): delta = G~'(U)^{-1} r with the space-varying
+        averaged Jacobian of U (plans built with field_jacobian=True)."""
+        self._check(u0, self.slice_shape, "u0")
+        self._check(U, self.shape, "U")
+        self._check(r, self.shape, "r")
+        d = torch.empty_like(r)
+        it = self.plan.field_jacobian_solve_raw(u0.data_ptr(), U.data_ptr(), r.data_ptr(), d.data_ptr(), inner_rtol,
+                                                inner_max, self._work_ptr(), self.plan.work_bytes, self._stream())
+        return d, it
 
     def time_eig(self):
         """(V, W, d): the plan's FP64 eigendecomposition of the time-step

@@ -141,3 +141,36 @@ def test_chord_steps_settle_the_step_equation(scheme):
         assert dt * np.max(np.abs(f)) <= 1e-14
         prev = U[k].reshape(-1)
     assert all(1 <= i <= stepper.NEWTON_MAXIT for i in iters)
+
+
+# ------------------------------------------ space-varying averaged Jacobian
+def test_jacobian_field_hand_case():
+    U = np.array([[[1.0, -2.0]], [[3.0, 0.0]]])   # two levels of a 1 x 2 grid
+    assert np.array_equal(aao.jacobian_field(U), np.array([[3.0 * (1 + 9) / 2, 3.0 * (4 + 0) / 2]]))
+    assert aao.jacobian_field(U).mean() == aao.mean_jacobian(U)
+
+
+def test_field_jacobian_with_a_constant_field_is_the_scalar_preconditioner():
+    from workloads import Problem
+    p = Problem(op="ch", dim=2, n=6, nt=4, dt=1e-5, eps=0.1, alpha=0.02)
+    a = aao.precond_matrix_field(p, np.full((6, 6), 0.37)).toarray()
+    b = aao.precond_matrix(p, 0.37).toarray()
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_field_jacobian_is_the_exact_jacobian_for_a_time_constant_iterate():
+    # When every level holds the same field w, the time average of J_s is J_s(w):
+    # with alpha = 0 the approximate Jacobian G~' is then the exact derivative of
+    # the residual map G (eq. jacobian1), checked by central differences.
+    from workloads import Problem
+    p = Problem(op="ch", dim=2, n=5, nt=3, dt=1e-4, eps=0.2, alpha=0.0)
+    rng = np.random.default_rng(21)
+    w = rng.uniform(-0.8, 0.8, p.slice_shape)
+    U = np.broadcast_to(w, p.shape).copy()
+    u0 = rng.uniform(-0.8, 0.8, p.slice_shape)
+    m = aao.precond_matrix_field(p, aao.jacobian_field(U)).toarray()
+    V = rng.standard_normal(p.shape)
+    h = 1e-6
+    # G = -residual (the residual is b - K(U))
+    dG = (-aao.residual(p, U + h * V, u0) + aao.residual(p, U - h * V, u0)) / (2 * h)
+    assert np.max(np.abs(m @ V.reshape(-1) - dG.reshape(-1))) <= 1e-6 * np.max(np.abs(dG))
