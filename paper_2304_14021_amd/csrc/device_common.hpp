@@ -50,6 +50,24 @@ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
   return mk((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
 }
 
+// a / b with the hardware reciprocal in FP32 (1 ulp) and an IEEE divide in
+// FP64; for the diagonal solves of the preconditioner.
+__device__ __forceinline__ float recip_fast(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip_fast(double d) { return 1.0 / d; }
+template <typename T>
+__device__ __forceinline__ cx<T> cdiv_fast(cx<T> a, cx<T> b) {
+  const T d = recip_fast(b.x * b.x + b.y * b.y);
+  return mk((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// Offset of mode q of level lev in a spectral array stored as panels of
+// 2^tps modes: panel q >> tps holds that range of modes for all nlev levels,
+// level-major.  tps = log2(modes per level) gives the plain [level][mode]
+// layout.
+__device__ __forceinline__ size_t panel_index(int lev, int q, int tps, int nlev) {
+  return ((size_t(q >> tps) * size_t(nlev) + size_t(lev)) << tps) + size_t(q & ((1 << tps) - 1));
+}
+
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 constexpr int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 

@@ -53,13 +53,65 @@ __device__ __forceinline__ void dft8(cx<T> (&v)[8]) {
   v[7] = sub(e3, o3);
 }
 
+// Twiddle accessors: exp(-2 pi i m / N) from a full table (each twiddle of
+// a butterfly read), or from two short tables as tw_hi[m / 32] * tw_lo[m % 32]
+// with the butterfly's other twiddles formed as powers of its first one
+// (a few ulp; fewer LDS reads and a table of 2 sqrt(N) entries).
+template <typename T>
+struct TwTable {
+  static constexpr bool POW = false;
+  const cx<T>* t;
+  __device__ __forceinline__ cx<T> operator()(int m) const { return t[m]; }
+};
+template <typename T>
+struct TwSplit {
+  static constexpr bool POW = true;
+  const cx<T>* hi;
+  const cx<T>* lo;
+  __device__ __forceinline__ cx<T> operator()(int m) const { return mul(hi[m >> 5], lo[m & 31]); }
+};
+
+// w[r] = w1^r, r = 1 .. R-1, by products of depth at most 3.
+template <typename T, int R>
+__device__ __forceinline__ void tw_powers(cx<T> (&w)[R], cx<T> w1) {
+  w[1] = w1;
+  if constexpr (R > 2) {
+    w[2] = mul(w1, w1);
+    w[3] = mul(w[2], w1);
+  }
+  if constexpr (R > 4) {
+    w[4] = mul(w[2], w[2]);
+    w[5] = mul(w[4], w1);
+    w[6] = mul(w[3], w[3]);
+    w[7] = mul(w[4], w[3]);
+  }
+}
+
+// Row of element m in the LDS buffer: with SKEW one padding row follows
+// every 8 rows, so that the stride-R row writes of a stage fall in different
+// banks when a row is narrow (32 bytes).
+template <bool SKEW>
+__host__ __device__ constexpr int zrow(int m) { return SKEW ? m + (m >> 3) : m; }
+template <bool SKEW>
+__host__ __device__ constexpr int zrows(int n) { return SKEW ? n + n / 8 : n; }
+
 // One Stockham stage of radix R (2, 4 or 8) on P sequences of length N
 // (SIGN -1 forward, +1 inverse, unnormalized).  Ns = product of the radices
-// of the previous stages.
-template <typename T, int N, int P, int ES, int NT, int R, int SIGN>
-__device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw, int Ns) {
+// of the previous stages (the first stage, Ns = 1, has no twiddles).
+template <typename T, int N, int P, int ES, int NT, int R, int SIGN, bool SKEW, int Ns, typename TW>
+__device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
   constexpr int W = (N / R) * P;
   constexpr int IPT = cdiv_i(W, NT);
+  // Rows t + r N/R and d + r Ns; with SKEW and N/R, Ns multiples of 8 the
+  // padding rows split off as constant strides (one address per item).  The
+  // first stage writes d = R t, d + r with r < R <= 8 in the same group of 8.
+  constexpr int SRC = SKEW ? (N / R) + (N / R) / 8 : N / R;
+  constexpr int DST = SKEW ? (Ns >= 8 ? Ns + Ns / 8 : 1) : Ns;
+  static_assert(!SKEW || Ns == 1 || Ns % 8 == 0, "stage strides");
+  auto src_row = [](int t, int r) {
+    if constexpr (!SKEW || (N / R) % 8 == 0) return zrow<SKEW>(t) + r * SRC;
+    else return zrow<SKEW>(t + r * (N / R));
+  };
   const int tid = threadIdx.x;
   cx<T> v[IPT][R];
 #pragma unroll
@@ -68,13 +120,22 @@ __device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw
     if ((W % NT == 0) || w < W) {
       const int t = w / P, p = w - (w / P) * P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = z[(t + r * (N / R)) * ES + p];
-      const int k = t & (Ns - 1);
-      const int step = k * (N / (Ns * R));
+      for (int r = 0; r < R; ++r) v[i][r] = z[src_row(t, r) * ES + p];
+      if constexpr (Ns > 1) {
+        const int k = t & (Ns - 1);
+        const int step = k * (N / (Ns * R));
+        if constexpr (TW::POW) {
+          cx<T> w[R];
+          tw_powers<T, R>(w, tw(step));
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const cx<T> w_ = tw[step * r];
-        v[i][r] = (SIGN < 0) ? mul(v[i][r], w_) : mulc(v[i][r], w_);
+          for (int r = 1; r < R; ++r) v[i][r] = (SIGN < 0) ? mul(v[i][r], w[r]) : mulc(v[i][r], w[r]);
+        } else {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const cx<T> w_ = tw(step * r);
+            v[i][r] = (SIGN < 0) ? mul(v[i][r], w_) : mulc(v[i][r], w_);
+          }
+        }
       }
       if constexpr (R == 2) {
         const cx<T> a = v[i][0], b = v[i][1];
@@ -96,7 +157,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw
       const int k = t & (Ns - 1);
       const int d = (t - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[(d + r * Ns) * ES + p] = v[i][r];
+      for (int r = 0; r < R; ++r) z[(zrow<SKEW>(d) + r * DST) * ES + p] = v[i][r];
     }
   }
   __syncthreads();
@@ -106,19 +167,26 @@ __device__ __forceinline__ void fft_stage(cx<T>* z, const cx<T>* __restrict__ tw
 // remaining factor.  Input and output in natural order (Stockham autosort).
 // Callers synchronize before the call (inputs written) and may read the
 // result right after it (the last stage ends with a barrier).
+template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW, int Ns, typename TW>
+__device__ __forceinline__ void fft_stages_from(cx<T>* z, const TW& tw) {
+  if constexpr (Ns * 8 <= N) {
+    fft_stage_tw<T, N, P, ES, NT, 8, SIGN, SKEW, Ns>(z, tw);
+    fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, Ns * 8>(z, tw);
+  } else if constexpr (Ns * 4 == N) {
+    fft_stage_tw<T, N, P, ES, NT, 4, SIGN, SKEW, Ns>(z, tw);
+  } else if constexpr (Ns * 2 == N) {
+    fft_stage_tw<T, N, P, ES, NT, 2, SIGN, SKEW, Ns>(z, tw);
+  }
+}
+
+template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW = false, typename TW>
+__device__ __forceinline__ void fft_lds_tw(cx<T>* z, const TW& tw) {
+  fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, 1>(z, tw);
+}
+
 template <typename T, int N, int P, int ES, int NT, int SIGN>
 __device__ __forceinline__ void fft_lds(cx<T>* z, const cx<T>* __restrict__ tw) {
-  constexpr int L = ilog2(N);
-  int Ns = 1;
-  if constexpr (L >= 3) {
-#pragma unroll
-    for (int s = 0; s < L / 3; ++s) {
-      fft_stage<T, N, P, ES, NT, 8, SIGN>(z, tw, Ns);
-      Ns *= 8;
-    }
-  }
-  if constexpr (L % 3 == 2) fft_stage<T, N, P, ES, NT, 4, SIGN>(z, tw, Ns);
-  if constexpr (L % 3 == 1) fft_stage<T, N, P, ES, NT, 2, SIGN>(z, tw, Ns);
+  fft_lds_tw<T, N, P, ES, NT, SIGN, false>(z, TwTable<T>{tw});
 }
 
 // Source index j of the element that the DCT-via-FFT reordering puts at

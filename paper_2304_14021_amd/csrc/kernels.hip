@@ -406,9 +406,17 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
 // tile of XB columns of one level, from Sin (type T) to Sout (type TO; the
 // same array when TO == T: the tile is read completely before it is written).  Columns 2c and 2c+1 are
 // packed into one complex sequence; consecutive threads take consecutive c.
-template <typename T, typename TO, int N, int XB, int NT, bool INV>
+// PANEL: the spectral side (output of the forward, input of the inverse) is
+// stored in panels of 2^tps modes; the other side is plain [level][mode].
+template <bool PANEL, int N>
+__device__ __forceinline__ size_t spec_off(int lev, int q, int tps, int nlev) {
+  if constexpr (PANEL) return panel_index(lev, q, tps, nlev);
+  else return size_t(lev) * (N * N) + q;
+}
+
+template <typename T, typename TO, int N, int XB, int NT, bool INV, bool PANEL>
 __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* __restrict__ done,
-                                              DctTables<T> dt) {
+                                              DctTables<T> dt, int tps) {
   if (done && *done) return;
   constexpr int C = XB / 2, ES = C, NBX = N / XB, K = N / 2 + 1;
   __shared__ __align__(16) cx<T> z[N * ES];
@@ -425,6 +433,9 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
                                             : int(blockIdx.x);
   const int lev = blk / NBX;
   const int x0 = (blk - lev * NBX) * XB;
+  const int nlev = nb / NBX;
+  // element (lev, q = row N + x); a pair (q, q + 1), q even, is contiguous in
+  // both layouts
   const T* base = Sin + size_t(lev) * N * N + x0;
   TO* obase = Sout + size_t(lev) * N * N + x0;
   if (!INV) {
@@ -450,9 +461,11 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
       T x1k, x2k, x1n, x2n;
       dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
-      *reinterpret_cast<cx<TO>*>(obase + size_t(k) * N + 2 * c) = mk(TO(x1k), TO(x2k));
+      *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev)) =
+          mk(TO(x1k), TO(x2k));
       if (k > 0 && k < N / 2)
-        *reinterpret_cast<cx<TO>*>(obase + size_t(N - k) * N + 2 * c) = mk(TO(x1n), TO(x2n));
+        *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev)) =
+            mk(TO(x1n), TO(x2n));
     }
   } else {
     constexpr int W = K * C, IT = cdiv_i(W, NT);
@@ -463,8 +476,8 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
       xk[i] = xn[i] = mk(T(0), T(0));
       if (w < W) {
         const int k = w / C, c = w - (w / C) * C;
-        xk[i] = *reinterpret_cast<const cx<T>*>(base + size_t(k) * N + 2 * c);
-        if (k) xn[i] = *reinterpret_cast<const cx<T>*>(base + size_t(N - k) * N + 2 * c);
+        xk[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev));
+        if (k) xn[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev));
       }
     }
     __syncthreads();  // s_tw / s_w complete
@@ -544,23 +557,51 @@ __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __
 //   sigma_{l,k} = lambda1_l + p_l lam_k + q_l lam_k^2,   l = 0..N_t/2,
 // (p_l = pco_l - c_bar for the CH operators), re-packed, transformed back and
 // scaled by a^{-j}/N_t.
+// LDS in FP64: the tile with one padding row after every 8 (the first FFT
+// stage writes rows 8 apart, which would otherwise hit the same banks) and
+// the twiddles as products of two short tables (indexed by m / 32 and
+// m mod 32), which leaves room for a third block per CU at N_t = 1024 than
+// the full table (measured 1.96 -> 1.69 ms at 512^2 x 1024).  In FP32 the
+// plain tile and the full table measured fastest.
 template <typename T, int NTT, int M, int NT>
 __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
   constexpr int C = M / 2;
-  __shared__ __align__(16) cx<T> z[NTT * C];
-  __shared__ cx<T> s_tw[NTT];
-  table_to_lds<T, NT, NTT>(s_tw, ta.tw);
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr bool SK = F64 && NTT >= 8;
+  constexpr int NLO = NTT < 32 ? NTT : 32, NHI = NTT < 32 ? 1 : NTT / 32;
+  __shared__ __align__(16) cx<T> z[zrows<SK>(NTT) * C];
+  __shared__ cx<T> s_lo[F64 ? NLO : 1];
+  __shared__ cx<T> s_hi[F64 ? NHI : 1];
+  __shared__ cx<T> s_tw[F64 ? 1 : NTT];
   const int tid = threadIdx.x;
-  // Tiles narrower than a 128-byte line share lines with their neighbours.
-  // Workgroups are dealt to the 8 XCDs round-robin; this order gives XCD x
-  // the contiguous range of tiles [x B/8, (x+1) B/8) (B tiles), so the tiles
-  // sharing a line read it through one L2.
+  if constexpr (F64) {
+    for (int i = tid; i < NLO + NHI; i += NT) {
+      if (i < NLO) s_lo[i] = ta.tw[i];
+      else s_hi[i - NLO] = ta.tw[32 * (i - NLO)];
+    }
+  } else {
+    table_to_lds<T, NT, NTT>(s_tw, ta.tw);
+  }
+  auto twiddles = [&]() {
+    if constexpr (F64) return TwSplit<T>{s_hi, s_lo};
+    else return TwTable<T>{s_tw};
+  };
+  const auto tws = twiddles();
+  // In a panel wider than the tile, tiles narrower than a 128-byte line
+  // share lines with their neighbours.  Workgroups are dealt to the 8 XCDs
+  // round-robin; this order gives XCD x the contiguous range of tiles
+  // [x B/8, (x+1) B/8) (B tiles), so the tiles sharing a line read it through
+  // one L2.  With panels of one tile each tile is a contiguous N_t x M block.
   const int nb = gridDim.x;
-  const int tile = (M * int(sizeof(T)) < 128 && (nb & 7) == 0) ? int(blockIdx.x & 7) * (nb >> 3) + int(blockIdx.x >> 3)
-                                                                 : int(blockIdx.x);
+  const int tp = 1 << ta.tps;
+  const int tile = (tp > M && M * int(sizeof(T)) < 128 && (nb & 7) == 0)
+                       ? int(blockIdx.x & 7) * (nb >> 3) + int(blockIdx.x >> 3)
+                       : int(blockIdx.x);
   const int col0 = tile * M;
-  const size_t ns = ta.ns;
+  // level j of this tile's modes starts at Sb + j * tp
+  T* const Sb = S + (size_t(col0 >> ta.tps) * NTT << ta.tps) + (col0 & (tp - 1));
+  const size_t rs = size_t(tp);
   constexpr int W = NTT * C, IT = cdiv_i(W, NT);
   // FP32: two complex values (16 bytes) per load and store
   constexpr bool V2 = std::is_same<T, float>::value && C % 2 == 0;
@@ -572,17 +613,18 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W2 % NT == 0 || w < W2) {
         const int j = w / C2, c = w - (w / C2) * C2;
-        x[i] = *reinterpret_cast<const float4*>(S + j * ns + col0 + 4 * c);
+        x[i] = *reinterpret_cast<const float4*>(Sb + j * rs + 4 * c);
       }
     }
 #pragma unroll
     for (int i = 0; i < IT2; ++i) {
       const int w = tid + i * NT;
       if (W2 % NT == 0 || w < W2) {
-        const int j = w / C2;
+        const int j = w / C2, c = w - (w / C2) * C2;
         const T s = ta.aj[j];
-        z[2 * w] = scale(mk(T(x[i].x), T(x[i].y)), s);
-        z[2 * w + 1] = scale(mk(T(x[i].z), T(x[i].w)), s);
+        cx<T>* zr = z + zrow<SK>(j) * C + 2 * c;
+        zr[0] = scale(mk(T(x[i].x), T(x[i].y)), s);
+        zr[1] = scale(mk(T(x[i].z), T(x[i].w)), s);
       }
     }
   } else {
@@ -593,57 +635,63 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W % NT == 0 || w < W) {
         const int j = w / C, c = w - (w / C) * C;
-        x[i] = *reinterpret_cast<const cx<T>*>(S + j * ns + col0 + 2 * c);
+        x[i] = *reinterpret_cast<const cx<T>*>(Sb + j * rs + 2 * c);
       }
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[w] = scale(x[i], ta.aj[w / C]);
+      if (W % NT == 0 || w < W) {
+        const int j = w / C, c = w - (w / C) * C;
+        z[zrow<SK>(j) * C + c] = scale(x[i], ta.aj[j]);
+      }
     }
   }
   __syncthreads();
-  fft_lds<T, NTT, C, C, NT, -1>(z, s_tw);
+  fft_lds_tw<T, NTT, C, C, NT, -1, SK>(z, tws);
   constexpr int WD = (NTT / 2 + 1) * C, ITD = cdiv_i(WD, NT);
-  // coefficients of every (l, c) item of this thread, loaded together
-  cx<T> l1v[ITD], plv[ITD], qlv[ITD];
-  T lk1v[ITD], lk2v[ITD];
+  static_assert(NT % C == 0, "a thread keeps one mode pair c");
+  // the mode pair of every item of this thread (NT is a multiple of C)
+  const int c = tid % C;
+  const int k1 = col0 + 2 * c, k2 = k1 + 1;
+  const T lk1 = ta.lamx[k1 % ta.nx] + ta.lamy[k1 / ta.nx];
+  const T lk2 = ta.lamx[k2 % ta.nx] + ta.lamy[k2 / ta.nx];
+  const T lk1s = lk1 * lk1, lk2s = lk2 * lk2;
   const double cbd = ta.cbar_mode ? (ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0;
+  const T cb = T(cbd);
+  // the level coefficients of every item of this thread, loaded together
+  cx<T> l1v[ITD], plv[ITD], qlv[ITD];
 #pragma unroll
   for (int i = 0; i < ITD; ++i) {
     const int w = tid + i * NT;
-    const int l = w < WD ? w / C : 0, c = w - (w / C) * C;
-    const int k1 = col0 + 2 * c, k2 = k1 + 1;
+    const int l = w < WD ? w / C : 0;
     l1v[i] = ta.lam1[l];
     plv[i] = ta.pco[l];
     qlv[i] = ta.qco[l];
-    lk1v[i] = ta.lamx[k1 % ta.nx] + ta.lamy[k1 / ta.nx];
-    lk2v[i] = ta.lamx[k2 % ta.nx] + ta.lamy[k2 / ta.nx];
   }
-  const T cb = T(cbd);
 #pragma unroll
   for (int i = 0; i < ITD; ++i) {
     const int w = tid + i * NT;
     if (w >= WD) continue;
-    const int l = w / C, c = w - (w / C) * C;
+    const int l = w / C;
     const int m = (NTT - l) & (NTT - 1);
-    const cx<T> zl = z[l * C + c];
-    const cx<T> zm = conj(z[m * C + c]);
+    const cx<T> zl = z[zrow<SK>(l) * C + c];
+    const cx<T> zm = conj(z[zrow<SK>(m) * C + c]);
     const cx<T> x1 = scale(add(zl, zm), T(0.5));
     const cx<T> x2 = scale(mul_mi(sub(zl, zm)), T(0.5));
-    const T lk1 = lk1v[i], lk2 = lk2v[i];
     const cx<T> l1 = l1v[i];
-    const cx<T> pl = mk(plv[i].x - cb, plv[i].y);
+    const cx<T> pl0 = plv[i];
     const cx<T> ql = qlv[i];
-    const cx<T> s1 = mk(l1.x + pl.x * lk1 + ql.x * lk1 * lk1, l1.y + pl.y * lk1 + ql.y * lk1 * lk1);
-    const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2 * lk2, l1.y + pl.y * lk2 + ql.y * lk2 * lk2);
-    const cx<T> y1 = cdiv(x1, s1);
-    const cx<T> y2 = cdiv(x2, s2);
-    z[l * C + c] = add(y1, mul_i(y2));
-    if (m != l) z[m * C + c] = add(conj(y1), mul_i(conj(y2)));
+    const cx<T> pl = mk(pl0.x - cb, pl0.y);
+    const cx<T> s1 = mk(l1.x + pl.x * lk1 + ql.x * lk1s, l1.y + pl.y * lk1 + ql.y * lk1s);
+    const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2s, l1.y + pl.y * lk2 + ql.y * lk2s);
+    const cx<T> y1 = cdiv_fast(x1, s1);
+    const cx<T> y2 = cdiv_fast(x2, s2);
+    z[zrow<SK>(l) * C + c] = add(y1, mul_i(y2));
+    if (m != l) z[zrow<SK>(m) * C + c] = add(conj(y1), mul_i(conj(y2)));
   }
   __syncthreads();
-  fft_lds<T, NTT, C, C, NT, +1>(z, s_tw);
+  fft_lds_tw<T, NTT, C, C, NT, +1, SK>(z, tws);
   if constexpr (V2) {
 #pragma unroll
     for (int i = 0; i < IT2; ++i) {
@@ -651,8 +699,9 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       if (W2 % NT == 0 || w < W2) {
         const int j = w / C2, c = w - (w / C2) * C2;
         const T s = ta.aij[j];
-        const cx<T> a = scale(z[2 * w], s), b = scale(z[2 * w + 1], s);
-        *reinterpret_cast<float4*>(S + j * ns + col0 + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
+        const cx<T>* zr = z + zrow<SK>(j) * C + 2 * c;
+        const cx<T> a = scale(zr[0], s), b = scale(zr[1], s);
+        *reinterpret_cast<float4*>(Sb + j * rs + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
       }
     }
   } else {
@@ -661,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W % NT == 0 || w < W) {
         const int j = w / C, c = w - (w / C) * C;
-        *reinterpret_cast<cx<T>*>(S + j * ns + col0 + 2 * c) = scale(z[w], ta.aij[j]);
+        *reinterpret_cast<cx<T>*>(Sb + j * rs + 2 * c) = scale(z[zrow<SK>(j) * C + c], ta.aij[j]);
       }
     }
   }
@@ -1221,14 +1270,30 @@ static hipError_t launch_rows_dct_n(const T* in, T* out, const DctTables<T>& dt,
 
 template <typename T, typename TO, int N>
 static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                                hipStream_t st) {
+                                hipStream_t st, int tpi, int tpo) {
   using C = col_cfg<T, N>;
   const int grid = nt * (N / C::XB);
-  if (!inv)
-    PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
-  else if constexpr (std::is_same<T, TO>::value)
-    PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done, dt);
-  else
+  // The plain side is [level][mode]; a panel of the spectral side holds whole
+  // pairs of modes and at most one level's modes; in place only when plain.
+  constexpr int PLAIN = 2 * ilog2(N);
+  const int tps = inv ? tpi : tpo;
+  if ((inv ? tpo : tpi) != PLAIN || tps < 1 || tps > PLAIN) return hipErrorInvalidValue;
+  if ((void*)Sin == (void*)Sout && tps != PLAIN) return hipErrorInvalidValue;
+  if (!inv) {
+    if (tps == PLAIN)
+      PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
+                  dt, tps);
+    else
+      PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
+                  dt, tps);
+  } else if constexpr (std::is_same<T, TO>::value) {
+    if (tps == PLAIN)
+      PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
+                  dt, tps);
+    else
+      PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
+                  dt, tps);
+  } else
     return hipErrorInvalidValue;
   PINT_CHECK_LAUNCH();
   return hipSuccess;
@@ -1274,8 +1339,8 @@ hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double*
 
 template <typename T, typename TO>
 hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                       hipStream_t st) {
-#define CC_(NN) launch_cols_n<T, TO, NN>(Sin, Sout, done, dt, nt, inv, st)
+                       hipStream_t st, int tps_in, int tps_out) {
+#define CC_(NN) launch_cols_n<T, TO, NN>(Sin, Sout, done, dt, nt, inv, st, tps_in, tps_out)
   PINT_SWITCH_N(CC_)
 #undef CC_
 }
@@ -1298,13 +1363,13 @@ hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& d
   if (!inv) {
     e = rows_dct_dispatch<T, 2>(n, in, out, dt, nt, false, st);
     if (e != hipSuccess) return e;
-    return launch_cols<T, T>(n, out, out, nullptr, dt, nt, false, st);
+    return launch_cols<T, T>(n, out, out, nullptr, dt, nt, false, st, 2 * ilog2(n), 2 * ilog2(n));
   }
   if (in != out) {
     e = hipMemcpyAsync(out, in, sizeof(T) * size_t(nt) * n * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
   }
-  e = launch_cols<T, T>(n, out, out, nullptr, dt, nt, true, st);
+  e = launch_cols<T, T>(n, out, out, nullptr, dt, nt, true, st, 2 * ilog2(n), 2 * ilog2(n));
   if (e != hipSuccess) return e;
   return rows_dct_dispatch<T, 2>(n, out, out, dt, nt, true, st);
 }
@@ -1336,11 +1401,38 @@ static hipError_t launch_time_m(T* S, const TimeArgs<T>& ta, hipStream_t st) {
 }
 
 template <typename T, int NTT>
-static hipError_t launch_time_nt(T* S, const TimeArgs<T>& ta, hipStream_t st) {
+static int time_tile_nt(int ns, int tile) {
   int m = time_cfg<T, NTT>::MDEF;
-  if (ta.tile > 0) m = ta.tile < time_cfg<T, NTT>::MMAX ? ta.tile : time_cfg<T, NTT>::MMAX;
-  while (m > 8 && (m > ta.ns || ta.ns % m != 0)) m /= 2;
-  if (ta.ns % m != 0) return hipErrorInvalidValue;
+  if (tile > 0) m = tile < time_cfg<T, NTT>::MMAX ? tile : time_cfg<T, NTT>::MMAX;
+  while (m > 8 && (m > ns || ns % m != 0)) m /= 2;
+  return ns % m == 0 ? m : 0;
+}
+
+template <typename T>
+static int time_tile_t(int nt, int ns, int tile) {
+  switch (nt) {
+    case 4: return time_tile_nt<T, 4>(ns, tile);
+    case 8: return time_tile_nt<T, 8>(ns, tile);
+    case 16: return time_tile_nt<T, 16>(ns, tile);
+    case 32: return time_tile_nt<T, 32>(ns, tile);
+    case 64: return time_tile_nt<T, 64>(ns, tile);
+    case 128: return time_tile_nt<T, 128>(ns, tile);
+    case 256: return time_tile_nt<T, 256>(ns, tile);
+    case 512: return time_tile_nt<T, 512>(ns, tile);
+    case 1024: return time_tile_nt<T, 1024>(ns, tile);
+    default: return 0;
+  }
+}
+
+int time_tile_modes(bool fp64, int nt, int ns, int tile) {
+  return fp64 ? time_tile_t<double>(nt, ns, tile) : time_tile_t<float>(nt, ns, tile);
+}
+
+template <typename T, int NTT>
+static hipError_t launch_time_nt(T* S, const TimeArgs<T>& ta, hipStream_t st) {
+  const int m = time_tile_nt<T, NTT>(ta.ns, ta.tile);
+  // the panel holds whole tiles and at most one level's modes
+  if (m == 0 || ta.tps < 0 || (1 << ta.tps) > ta.ns || (1 << ta.tps) % m != 0) return hipErrorInvalidValue;
   switch (m) {
     case 64: return launch_time_m<T, NTT, 64>(S, ta, st);
     case 32: return launch_time_m<T, NTT, 32>(S, ta, st);
@@ -1477,11 +1569,11 @@ template hipError_t launch_rows_inv<float>(int, int, const UpdArgs&, const float
 template hipError_t launch_rows_inv<double>(int, int, const UpdArgs&, const double*, double*,
                                             const DctTables<double>&, int, int, hipStream_t);
 template hipError_t launch_cols<float, float>(int, const float*, float*, const int*, const DctTables<float>&, int,
-                                              bool, hipStream_t);
+                                              bool, hipStream_t, int, int);
 template hipError_t launch_cols<double, double>(int, const double*, double*, const int*, const DctTables<double>&,
-                                                int, bool, hipStream_t);
+                                                int, bool, hipStream_t, int, int);
 template hipError_t launch_cols<double, float>(int, const double*, float*, const int*, const DctTables<double>&,
-                                               int, bool, hipStream_t);
+                                               int, bool, hipStream_t, int, int);
 template hipError_t launch_dct<float>(int, int, const float*, float*, const DctTables<float>&, int, bool,
                                       hipStream_t);
 template hipError_t launch_dct<double>(int, int, const double*, double*, const DctTables<double>&, int, bool,

@@ -119,6 +119,8 @@ struct TimeArgs {
   const int* done;
   int nx, ns, cbar_mode;
   int tile;           // cap on the spatial modes per workgroup (0 = automatic)
+  int tps;            // log2 of the spectral panel width P: mode k of level n
+                      // at ((k / P) N_t + n) P + k mod P (P = ns: [level][mode])
 };
 
 struct InitArgs {
@@ -153,10 +155,15 @@ template <typename T>
 hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double* dout, const DctTables<T>& dt,
                            int nt, int mode, hipStream_t st);
 // Column pass computing in T, reading Sin (T) and writing Sout (TO; TO == T
-// for the inverse).  Sin == Sout is allowed when TO == T.
+// for the inverse).  tps_in / tps_out: log2 of the panel width of each side's
+// layout (log2(n^2): plain [level][mode]).  Sin == Sout is allowed when
+// TO == T and the two layouts are the same.
 template <typename T, typename TO>
 hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                       hipStream_t st);
+                       hipStream_t st, int tps_in, int tps_out);
+// Spatial modes per workgroup of the FFT time solve (its panel width when
+// the spectral array is tiled).
+int time_tile_modes(bool fp64, int nt, int ns, int tile);
 template <typename T>
 hipError_t launch_dct(int dim, int n, const T* in, T* out, const DctTables<T>& dt, int nt, bool inv,
                       hipStream_t st);

@@ -80,6 +80,10 @@ SOLVE_CASES = [
     Problem(op="linear_ch", dim=2, n=128, nt=1024, dt=1e-6, eps=0.05, beta=0.5, alpha=1e-3),
     Problem(op="ch", dim=2, n=256, nt=16, dt=1e-6, eps=0.01, alpha=1e-3),
     Problem(op="linear_ch", dim=2, n=512, nt=8, dt=1e-6, eps=0.0075, beta=0.5, alpha=1e-3),
+    # N_t >= 512 in 2D: the FP32 and FP64 plans keep the spectral array in
+    # panels one 128-byte line wide, each holding several time-solve tiles
+    Problem(op="ch", dim=2, n=16, nt=512, dt=1e-6, eps=0.05, alpha=1e-3),
+    Problem(op="biharmonic", dim=2, n=8, nt=1024, dt=1e-5, theta=0.5, alpha=1e-3),
 ]
 
 
