@@ -266,7 +266,10 @@ def dct2_matrix(n: int) -> np.ndarray:
     Its rows are the eigenvectors of the cell-centred Neumann Laplacian."""
     k = np.arange(n)[:, None]
     j = np.arange(n)[None, :]
-    q = np.cos(np.pi * k * (2 * j + 1) / (2.0 * n)) * np.sqrt(2.0 / n)
+    # cos has period 4n in the integer k (2j+1): reduce it exactly first, so
+    # the argument stays below 2 pi and carries no rounding of order k j u
+    m = (k * (2 * j + 1)) % (4 * n)
+    q = np.cos(np.pi * m / (2.0 * n)) * np.sqrt(2.0 / n)
     q[0, :] = np.sqrt(1.0 / n)
     return q
 

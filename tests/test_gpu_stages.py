@@ -9,8 +9,15 @@ working precisions, 1D and 2D, and the smallest and largest supported sizes.
 Tolerances (derived from the arithmetic):
 * residual: FP64 on both sides, each entry a short sum of O(1) terms scaled by
   1/dt and 1/h^4: 1e-13 relative to max|r|.
-* DCT: orthonormal, O(log N) rounding steps of unit roundoff u per output:
-  FP64 4 u log2(N) ~ 1e-14, FP32 8 u log2(N)^2 (u = 2^-24), relative to max|x|.
+* DCT: orthonormal (the 2-norm of every batch is kept), computed by a radix-8
+  FFT of log2(N_s) butterfly levels over the passes, each rounding its outputs
+  by about u (u = 2^-53 FP64, 2^-24 FP32) relative to their size, so the error
+  of an output is of order u sqrt(log2 N_s) times the RMS of the input.  The
+  bound, also for the largest of up to 2^28 outputs (about 6 standard
+  deviations): 8 u log2(N_s) x RMS(x), plus 16 u64 sqrt(N) x RMS(x) for the
+  oracle's own FP64 dense products (N-term sums).  A twiddle or post-twiddle
+  table rounded to BF16 or FP16 (or a wrong entry) exceeds it by orders of
+  magnitude.
 * time solve / preconditioner: the Gamma_alpha scaling turns an absolute
   rounding error of u * max_j |a^j x_j| at time level j into a relative one
   multiplied by a^{-(N_t-1)} < 1/alpha; the bound used is
@@ -66,6 +73,16 @@ def test_residual_stage(p):
     assert err < 1e-13, err
 
 
+def _idct2(y, dim):
+    """Inverse of the oracle's orthonormal DCT-II: the transposed matrix along
+    each transformed axis."""
+    q = aao.dct2_matrix(y.shape[-1])
+    x = y @ q
+    if dim == 2:
+        x = np.swapaxes(np.swapaxes(x, -1, -2) @ q, -1, -2)
+    return x
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("p", CASES, ids=IDS)
 def test_dct_stage(p, prec):
@@ -78,11 +95,16 @@ def test_dct_stage(p, prec):
     y = host(s.dct(xd))
     xin = host(xd).astype(np.float64)
     ref = aao.dct2(xin, p.dim)
-    lg = math.log2(p.n)
-    tol = 4 * U64 * lg if prec == "fp64" else 8 * U32 * lg * lg
-    assert np.max(np.abs(y - ref)) <= tol * np.max(np.abs(xin)) * math.sqrt(p.ns), "forward"
-    z = host(s.dct(to_dev(ref, tdt), inverse=True))
-    assert np.max(np.abs(z - xin)) <= tol * np.max(np.abs(ref)) * math.sqrt(p.ns), "inverse"
+    u = U64 if prec == "fp64" else U32
+    tol = 8 * u * math.log2(p.ns) + 16 * U64 * math.sqrt(p.n)
+    rms = float(np.sqrt(np.mean(xin ** 2)))
+    ef = np.max(np.abs(y - ref)) / rms
+    zin = host(to_dev(ref, tdt)).astype(np.float64)
+    z = host(s.dct(to_dev(zin, tdt), inverse=True))
+    ei = np.max(np.abs(z - _idct2(zin, p.dim))) / float(np.sqrt(np.mean(zin ** 2)))
+    say(f"  forward {ef / u:.2f} u x RMS, inverse {ei / u:.2f} u x RMS (bound {tol / u:.1f} u)")
+    assert ef <= tol, ("forward", ef, tol)
+    assert ei <= tol, ("inverse", ei, tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
