@@ -173,7 +173,7 @@ def _spin_until(t_target):
             time.sleep(d - 1e-3)
 
 
-def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, graphs=True, alpha=0.0):
+def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, graphs=True, alpha=0.0, light=False):
     """The served stream through the library's serving loop.
 
     Closed loop: all requests queued at once; the saturation rate is requests
@@ -182,7 +182,7 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
     submitted at its arrival time; latency = completion - scheduled arrival.
     Device-resident requests (u0 and U in HBM, no host copies) unless
     stated; the host-buffer variant is measured once for the PCIe-inclusive
-    rate."""
+    rate.  light: saturation and 0.5x only, plus the oracle check."""
     import numpy as np
     import torch
     from paper_2304_14021_amd import Server, Solver
@@ -247,7 +247,7 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
         sat = summary(w, lat, reps)
         out["saturation"] = sat
         log(f"serving saturation: {json.dumps(sat)}")
-        for f in (0.5, 0.9):
+        for f in ((0.5,) if light else (0.5, 0.9)):
             rate = f * sat["req_per_s"]
             w, lat, reps = run(srv, rate)
             out[f"load_{f}"] = summary(w, lat, reps, rate)
@@ -255,14 +255,15 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
         st = srv.stats()
         out["server_stats"] = {k: st[k] for k in ("graphs_captured", "graph_updates", "graph_launches",
                                                   "pool_peak", "failed")}
-        # PCIe-inclusive: u0 from and U back to host memory, closed loop
-        run(srv, None, host_io=True)
-        w, lat, reps = run(srv, None, host_io=True)
-        out["host_io_saturation"] = summary(w, lat, reps)
+        if not light:
+            # PCIe-inclusive: u0 from and U back to host memory, closed loop
+            run(srv, None, host_io=True)
+            w, lat, reps = run(srv, None, host_io=True)
+            out["host_io_saturation"] = summary(w, lat, reps)
     # one request at a time, each timed alone (plan and workspace made
     # beforehand, not timed): what the same stream costs without batching
     solo = 0.0
-    for i, r in enumerate(reqs):
+    for i, r in enumerate([] if light else reqs):
         s = Solver.for_problem(r.problem, precision=precision, device=dev)
         s.solve(u0d[i], Ud[i])
         torch.cuda.synchronize()
@@ -271,8 +272,9 @@ def serving_bench(dev, precision, slots, pool_gib, n_requests, oracle_checks, gr
         torch.cuda.synchronize()
         solo += time.perf_counter() - ts
         del s
-    out["one_at_a_time"] = {"dof_per_s": float(dof.sum()) / solo, "req_per_s": len(reqs) / solo,
-                            "note": "sum of standalone solve times of the same requests"}
+    if not light:
+        out["one_at_a_time"] = {"dof_per_s": float(dof.sum()) / solo, "req_per_s": len(reqs) / solo,
+                                "note": "sum of standalone solve times of the same requests"}
     # served results (a fresh device-resident pass) against stored data of
     # the oracle's sequential solutions of the smallest requests
     errs = []
@@ -567,6 +569,11 @@ def main():
         out["serving"] = serving_bench(dev, args.serve_precision, args.serve_slots, args.serve_pool_gib,
                                        args.serve_requests, oracle_checks=8, graphs=not args.serve_no_graphs,
                                        alpha=args.serve_alpha)
+        # the same stream in the other precision (FP64 <-> refined mixed)
+        alt = "mixed" if args.serve_precision == "fp64" else "fp64"
+        out["serving_" + alt] = serving_bench(dev, alt, args.serve_slots, args.serve_pool_gib, args.serve_requests,
+                                              oracle_checks=8, graphs=not args.serve_no_graphs,
+                                              alpha=args.serve_alpha, light=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name)
     print(json.dumps(out), flush=True)
