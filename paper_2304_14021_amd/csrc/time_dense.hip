@@ -247,8 +247,230 @@ __global__ __launch_bounds__(256) void k_time_dense(float* __restrict__ S, TimeA
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 kinds at N_t >= 256: both operand tiles live in LDS as BF16,
+// transposed ([column][k], row stride N_t + 8), so that a lane's B operand
+// (8 consecutive k of one column) is one 16-byte read, and the FP32 -> BF16
+// rounding (and the hi/lo split) is done once per element: when the tile is
+// staged, and when y' is written back after the divide.  NW waves and NCB
+// column blocks of 32 modes; wave w owns the RPW row blocks from w RPW and
+// every column block, so each A fragment (W from global memory) feeds NCB
+// MFMAs.
+template <int NTT, int NW, int NCB>
+struct b16_cfg {
+  static constexpr int NB = 32 * NCB, LDK = NTT + 8, NT = 64 * NW, RPW = NTT / 32 / NW;
+};
+
+template <int KIND, int NTT, int RPW, int NCB>
+__device__ __forceinline__ void gemm_b16(f32x16 (&acc)[RPW][NCB], int rb0, const __bf16* __restrict__ ah,
+                                         const __bf16* __restrict__ al, const __bf16* xh, const __bf16* xl) {
+  constexpr bool X3 = KIND == DK_BF16X3;
+  constexpr int LDK = NTT + 8;
+  // MFMA k-steps (of 16) per chunk: the A fragments of two chunks (this one
+  // and the next, in flight) stay within the register budget
+  constexpr int KS = RPW * NCB * (X3 ? 2 : 1) >= 8 ? 1 : 2;
+  constexpr int NCH = NTT / (16 * KS);
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 31, hi = lane >> 5;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[r][c] = f32x16{};
+  bf16x8 ch[KS][RPW], cl[KS][RPW], nh[KS][RPW], nl[KS][RPW];
+  auto load = [&](int c, bf16x8 (&h)[KS][RPW], bf16x8 (&l)[KS][RPW]) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int kb = (c * KS + s) * 16 + 8 * hi;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const size_t ao = size_t((rb0 + r) * 32 + li) * NTT + kb;
+        h[s][r] = *reinterpret_cast<const bf16x8*>(ah + ao);
+        if constexpr (X3) l[s][r] = *reinterpret_cast<const bf16x8*>(al + ao);
+      }
+    }
+  };
+  load(0, ch, cl);
+  for (int c = 0; c < NCH; ++c) {
+    if (c + 1 < NCH) load(c + 1, nh, nl);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int kb = (c * KS + s) * 16 + 8 * hi;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(xh + (cb * 32 + li) * LDK + kb);
+        bf16x8 bl;
+        if constexpr (X3) bl = *reinterpret_cast<const bf16x8*>(xl + (cb * 32 + li) * LDK + kb);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          acc[r][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch[s][r], bh, acc[r][cb], 0, 0, 0);
+          if constexpr (X3) {
+            acc[r][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch[s][r], bl, acc[r][cb], 0, 0, 0);
+            acc[r][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl[s][r], bh, acc[r][cb], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        ch[s][r] = nh[s][r];
+        if constexpr (X3) cl[s][r] = nl[s][r];
+      }
+  }
+}
+
+// BF16 hi part (round to nearest even) and, for the split, the BF16 of the
+// remainder.
+template <bool X3>
+__device__ __forceinline__ void split_bf16(float x, __bf16& h, __bf16& l) {
+  h = __bf16(x);
+  if constexpr (X3) l = __bf16(x - float(h));
+}
+
+template <int KIND, int NTT, int NW, int NCB>
+__global__ __launch_bounds__(64 * NW) void k_time_dense_b16(float* __restrict__ S, TimeArgs<float> ta,
+                                                             DenseArgs da) {
+  if (ta.done && *ta.done) return;
+  using C = b16_cfg<NTT, NW, NCB>;
+  constexpr bool X3 = KIND == DK_BF16X3;
+  constexpr int NB = C::NB, LDK = C::LDK, NT = C::NT, RPW = C::RPW;
+  static_assert(RPW >= 1 && (NTT / 32) % NW == 0, "row blocks per wave");
+  __shared__ __align__(16) __bf16 xh[NB * LDK];
+  __shared__ __align__(16) __bf16 xl[X3 ? NB * LDK : 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col0 = blockIdx.x * NB;
+  const size_t ns = ta.ns;
+  const int rb0 = wave * RPW;
+
+  // stage: item (k8, n) = S[8 k8 .. 8 k8 + 7][col0 + n] -> 16 bytes of row n
+  {
+    constexpr int ITEMS = (NTT / 8) * NB, PER = ITEMS / NT;
+    static_assert(ITEMS % NT == 0, "stage split");
+    constexpr int BATCH = PER < 4 ? PER : 4;
+    static_assert(PER % BATCH == 0, "stage batches");
+#pragma unroll 1
+    for (int b0 = 0; b0 < PER; b0 += BATCH) {
+      float v[BATCH][8];
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int w = tid + (b0 + j) * NT;
+        const int k8 = w / NB, n = w - (w / NB) * NB;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[j][e] = S[size_t(8 * k8 + e) * ns + col0 + n];
+      }
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int w = tid + (b0 + j) * NT;
+        const int k8 = w / NB, n = w - (w / NB) * NB;
+        bf16x8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 he, le;
+          split_bf16<X3>(v[j][e], he, le);
+          h[e] = he;
+          if constexpr (X3) l[e] = le;
+        }
+        *reinterpret_cast<bf16x8*>(xh + n * LDK + 8 * k8) = h;
+        if constexpr (X3) *reinterpret_cast<bf16x8*>(xl + n * LDK + 8 * k8) = l;
+      }
+    }
+  }
+  __syncthreads();
+
+  f32x16 acc[RPW][NCB];
+  gemm_b16<KIND, NTT, RPW, NCB>(acc, rb0, static_cast<const __bf16*>(da.wf_hi),
+                                 static_cast<const __bf16*>(da.wf_lo), xh, xl);
+
+  // divide the pairs (rows 2l, 2l+1) by sigma_{l,k} in the accumulators
+  const float cbar = ta.cbar_mode ? float(ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0f;
+  float lk[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int k = col0 + cb * 32 + (lane & 31);
+    lk[cb] = ta.lamx[k % ta.nx] + ta.lamy[k / ta.nx];
+  }
+  // one pair of rows at a time: its coefficients serve every column block;
+  // the empty asm keeps the compiler from hoisting the coefficient loads of
+  // all row blocks at once (registers)
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) {
+      const int row = (rb0 + r) * 32 + acc_row(i, lane);  // even
+      const int l = row >> 1;
+      // l = 0: the real pair Re y_0 / sigma_0 and Re y_{N_t/2} / sigma_{N_t/2}
+      const int l2 = l == 0 ? NTT / 2 : l;
+      const cx<float> l1 = ta.lam1[l], p = ta.pco[l], qq = ta.qco[l];
+      const cx<float> l1h = ta.lam1[l2], ph = ta.pco[l2], qh = ta.qco[l2];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float x = lk[cb];
+        float a0 = acc[r][cb][i], a1 = acc[r][cb][i + 1];
+        if (l == 0) {
+          a0 = a0 / (l1.x + (p.x - cbar) * x + qq.x * x * x);
+          a1 = a1 / (l1h.x + (ph.x - cbar) * x + qh.x * x * x);
+        } else {
+          const cx<float> sg = mk(l1.x + (p.x - cbar) * x + qq.x * x * x, l1.y + p.y * x + qq.y * x * x);
+          const cx<float> y = cdiv(mk(a0, a1), sg);
+          a0 = y.x;
+          a1 = y.y;
+        }
+        acc[r][cb][i] = a0;
+        acc[r][cb][i + 1] = a1;
+      }
+    }
+  }
+  __syncthreads();  // every wave is done reading the staged tile
+  // y' back to LDS, transposed: rows acc_row(4g .. 4g+3) are consecutive
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int row = (rb0 + r) * 32 + acc_row(4 * g, lane);
+        const int n = cb * 32 + (lane & 31);
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          __bf16 he, le;
+          split_bf16<X3>(acc[r][cb][4 * g + e], he, le);
+          h[e] = he;
+          if constexpr (X3) l[e] = le;
+        }
+        *reinterpret_cast<bf16x4*>(xh + n * LDK + row) = h;
+        if constexpr (X3) *reinterpret_cast<bf16x4*>(xl + n * LDK + row) = l;
+      }
+  __syncthreads();
+
+  gemm_b16<KIND, NTT, RPW, NCB>(acc, rb0, static_cast<const __bf16*>(da.wb_hi),
+                                 static_cast<const __bf16*>(da.wb_lo), xh, xl);
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int n = (rb0 + r) * 32 + acc_row(i, lane);
+        S[size_t(n) * ns + col0 + cb * 32 + (lane & 31)] = acc[r][cb][i];
+      }
+}
+
 template <int KIND, int NTT>
 hipError_t launch_dense_nt(float* S, const TimeArgs<float>& ta, const DenseArgs& da, hipStream_t st) {
+  if constexpr (KIND != DK_F32 && NTT >= 256) {
+    // BF16 kinds: LDS-resident BF16 tiles; 64 columns for the single product,
+    // 32 for the split (its hi and lo tiles), 8 waves
+    constexpr int NCB = KIND == DK_BF16 ? 2 : 1;
+    using C = b16_cfg<NTT, 8, NCB>;
+    if (!da.direct && ta.ns % C::NB == 0) {
+      PINT_LAUNCH((k_time_dense_b16<KIND, NTT, 8, NCB>), dim3(ta.ns / C::NB), dim3(C::NT), 0, st, S, ta, da);
+      return hipGetLastError();
+    }
+  }
   constexpr int NB = dense_nb(NTT);
   if (ta.ns % NB != 0) return hipErrorInvalidValue;
   PINT_LAUNCH((k_time_dense<KIND, NTT>), dim3(ta.ns / NB), dim3(256), 0, st, S, ta, da);
