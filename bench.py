@@ -33,9 +33,11 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # dense, MI355X
 BF16_ALPHA = 1e-2  # alpha of the BF16 runs (coarser contraction, larger alpha)
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives),
-# profiles/c5_fp32_hbm_traffic.md.  Valid for the kernel as measured: drop the
-# entry when that kernel changes.
-MEASURED_TRAFFIC = {("c5", "fp32", "rows_fwd"): (1445529.0 * 2.0 + 1050624.0) * 1024}
+# profiles/c5_fp32_hbm_traffic.md, c2_fp64_hbm_traffic.md, c2_mixed_hbm_traffic.md.
+# Valid for the kernel as measured: drop the entry when that kernel changes.
+MEASURED_TRAFFIC = {("c5", "fp32", "rows_fwd"): (1445529.0 * 2.0 + 1050624.0) * 1024,
+                    ("c2", "fp64", "rows_fwd"): (8759.7 * 2.0 + 16400.0) * 1024,
+                    ("c2", "mixed", "rows_fwd"): (11597.0 * 2.0 + 16400.0) * 1024}
 PREC_DESC = {
     "mixed": "FP64 residual, FP64 forward DCT, FP32 time FFT solve and inverse DCT, FP64 update "
              "(iterative refinement)",
