@@ -236,8 +236,9 @@ int pint_plan_alpha(const pint_plan* plan, double* alpha);
 /*
  * Full solve: runs the outer iteration (residual, forward DCT-II, time
  * transform + shifted divide + inverse, inverse DCT + FP64 update, reductions
- * and stop rule) until the estimated relative error is below rtol or
- * max_iter is reached.
+ * and stop rule) until the estimated relative error is below rtol (and the
+ * FP64 residual norm has not grown over the last sweep) or max_iter is
+ * reached.
  *   d_u0    [N_y][N_x] FP64 initial datum u_0.
  *   d_U     [N_t][N_y][N_x] FP64, initial guess on entry (or filled from u0
  *           with PINT_FLAG_INIT_BROADCAST_U0), solution on exit.  Also written

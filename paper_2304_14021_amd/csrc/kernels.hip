@@ -720,7 +720,8 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
 // a7.  One workgroup: per level, sum the block partials; then max over levels
 //   upd  = max_n ||delta_n||_2,  unrm = max_n ||u_n||_2,  rel = upd / unrm
 //   rho  = upd_k / upd_{k-1};  est = rho/(1-rho) * rel
-// stop when est <= safety * rtol (k >= 2, rho < 1) or rel <= 1e-3 rtol;
+// stop when est <= safety * rtol (k >= 2, rho < 1) and the FP64 residual
+// norm max_n ||r_n||_2 has not grown over the last sweep, or rel <= 1e-3 rtol;
 // diverged on NaN/Inf or when the update grows 1e3-fold over the first one.
 // The scalar averaged Jacobian for the next time solve is mean(3 u^2).
 // Control-record fields the stop rule reads, loaded by thread 0 before the
@@ -840,10 +841,14 @@ __device__ void finalize_control(const FinArgs& f, double* red, double (&v)[4], 
   const double upd_first = k == 0 ? upd : c0.upd_first;
   if (k == 0) c->upd_first = upd;
   c->upd_prev = upd;
+  // The rate estimate alone could stop on one sweep whose update ratio dips;
+  // it also needs the FP64 residual of this sweep's iterate not to have grown
+  // over the previous sweep's.
+  const bool res_ok = k == 0 || k - 1 >= PINT_HIST_DEV || !(res > c->res_hist[k - 1]);
   if (bad || (k >= 2 && upd > 1e3 * upd_first)) {
     c->status = PINT_EDIVERGED;
     c->done = 1;
-  } else if (est <= f.safety * f.rtol || rel <= 1e-3 * f.rtol) {
+  } else if ((est <= f.safety * f.rtol && res_ok) || rel <= 1e-3 * f.rtol) {
     c->status = PINT_OK;
     c->done = 1;
   } else if (f.stagnate && k >= 2 && c0.upd_prev > 0.0 && upd > 0.5 * c0.upd_prev) {
