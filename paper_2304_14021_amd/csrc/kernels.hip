@@ -23,6 +23,7 @@
 #include "pint.h"
 #include "pint_kernels.hpp"
 #include "fft_lds.hpp"
+#include "stop_rule.hpp"
 
 #include <algorithm>
 #include <cstdlib>
@@ -830,34 +831,26 @@ __device__ void finalize_control(const FinArgs& f, double* red, double (&v)[4], 
   }
   c->iter = k + 1;
   c->c_bar = cbar;
-  const bool bad = !(upd == upd) || !(unrm == unrm) || !(cbar == cbar) || upd > 1e300 || unrm > 1e300;
-  double est = 1e300;
-  if (k >= 1 && c0.upd_prev > 0.0) {
-    const double rho = upd / c0.upd_prev;
-    if (rho < 1.0) est = rho / (1.0 - rho) * rel;
-  }
-  if (upd == 0.0) est = 0.0;
+  StopIn si;
+  si.k = k;
+  si.upd = upd;
+  si.unrm = unrm;
+  si.res = res;
+  si.cbar = cbar;
+  si.upd_prev = c0.upd_prev;
+  si.upd_first = c0.upd_first;
+  si.res_prev = (k >= 1 && k - 1 < PINT_HIST_DEV) ? c->res_hist[k - 1] : -1.0;
+  si.rtol = f.rtol;
+  si.safety = f.safety;
+  si.stagnate = f.stagnate;
+  si.max_iter = f.max_iter;
+  const StopOut so = stop_rule(si);
+  const double est = so.est;
   c->est = est;
-  const double upd_first = k == 0 ? upd : c0.upd_first;
   if (k == 0) c->upd_first = upd;
   c->upd_prev = upd;
-  // The rate estimate alone could stop on one sweep whose update ratio dips;
-  // it also needs the FP64 residual of this sweep's iterate not to have grown
-  // over the previous sweep's.
-  const bool res_ok = k == 0 || k - 1 >= PINT_HIST_DEV || !(res > c->res_hist[k - 1]);
-  if (bad || (k >= 2 && upd > 1e3 * upd_first)) {
-    c->status = PINT_EDIVERGED;
-    c->done = 1;
-  } else if ((est <= f.safety * f.rtol && res_ok) || rel <= 1e-3 * f.rtol) {
-    c->status = PINT_OK;
-    c->done = 1;
-  } else if (f.stagnate && k >= 2 && c0.upd_prev > 0.0 && upd > 0.5 * c0.upd_prev) {
-    // unrefined mode: the update stopped contracting, the iterate sits on
-    // its working-precision plateau
-    c->status = PINT_OK;
-    c->done = 1;
-  } else if (k + 1 >= f.max_iter) {
-    c->status = PINT_ENOCONV;
+  if (so.done) {
+    c->status = so.status;
     c->done = 1;
   }
   if (f.host) {
