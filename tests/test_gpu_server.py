@@ -281,3 +281,26 @@ def test_served_dense_and_fft_requests_of_one_shape():
         Ud, rrep = s.solve(to_dev(u0))
         assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
         assert np.array_equal(U, host(Ud)), f"{tp} eps {e}"
+
+
+def test_served_panel_layout_requests():
+    # 2D requests with N_t >= 512 keep their time solve's spectral array in
+    # line-wide panels (a second spectral buffer in the request's pool block):
+    # served beside plain-layout ones, each equals its standalone solve bit for
+    # bit and the sequential oracle within 1e-10
+    probs = [Problem(op="ch", dim=2, n=16, nt=512, dt=1e-6, eps=0.05, alpha=1e-3),
+             Problem(op="biharmonic", dim=2, n=8, nt=1024, dt=1e-5, theta=0.5, alpha=1e-3),
+             Problem(op="linear_ch", dim=2, n=16, nt=64, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)]
+    rng = np.random.default_rng(29)
+    u0s = [rng.uniform(-0.3, 0.3, p.slice_shape) for p in probs]
+    jobs = [(p, u, prec) for p, u in zip(probs, u0s) for prec in PRECS]
+    say(f"served panel-layout requests: {[(p.op[:3], p.n, p.nt, prec) for p, _, prec in jobs]}")
+    with Server(1 << 28, max_active=3, device=dev()) as srv:
+        ts = [srv.submit(p, u, precision=prec) for p, u, prec in jobs]
+        res = [srv.wait(t, timeout_ms=120000) for t in ts]
+    for (p, u0, prec), (U, rep) in zip(jobs, res):
+        ref, rrep = _solo(p, u0, prec)
+        assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
+        assert np.array_equal(U, ref), f"{p.op} nt {p.nt} {prec}"
+        err = stepper.rel_err(U, stepper.sequential(p, u0))
+        assert err <= 1e-10, (p.op, p.nt, prec, err)

@@ -57,6 +57,27 @@ def test_noalloc_equals_pint_solve_two_calls(prec):
         assert err <= 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "mixed"])
+def test_noalloc_panel_layout(prec):
+    # N_t >= 512 in 2D: the spectral array of the time solve is kept in
+    # line-wide panels, a second spectral buffer in the static workspace; then
+    # a smaller plain-layout call on the same workspace
+    first = Problem(op="ch", dim=2, n=16, nt=512, dt=1e-6, eps=0.05, alpha=1e-3)
+    second = Problem(op="linear_ch", dim=2, n=16, nt=64, dt=1e-5, eps=0.05, beta=0.5, alpha=1e-3)
+    rng = np.random.default_rng(37)
+    for p, amp in ((first, 0.3), (second, 0.05)):
+        u0 = rng.uniform(-amp, amp, p.slice_shape)
+        say(f"noalloc {prec} {p}")
+        U, rep = _noalloc(p, prec, u0)
+        s = Solver.for_problem(p, precision=prec, device=dev())
+        Ur, rrep = s.solve(to_dev(u0))
+        err = stepper.rel_err(U, stepper.sequential(p, u0))
+        say(f"  iterations {rep['iterations']} (pint_solve {rrep['iterations']}), err vs oracle {err:.2e}")
+        assert rep["status"] == 0 and rep["iterations"] == rrep["iterations"]
+        assert np.array_equal(U, host(Ur))
+        assert err <= 1e-10
+
+
 def test_noalloc_rejects_too_large_and_flags():
     lib = _pint.lib()
     p = _pint.make_problem("linear_ch", 2, 256, 256, 1e-5, eps=0.05, beta=0.5, alpha=1e-3, precision="fp64")
