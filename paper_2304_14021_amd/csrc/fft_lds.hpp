@@ -1,7 +1,7 @@
 // Batched transforms on data resident in LDS: Stockham FFT (radix-8 stages,
-// then one radix-4 or radix-2 stage for the remaining factor) and the
-// orthonormal DCT-II / DCT-III of real sequences computed through one complex
-// FFT per pair of sequences.
+// or radix-16 ones on request, then one radix-4 or radix-2 stage for the
+// remaining factor) and the orthonormal DCT-II / DCT-III of real sequences
+// computed through one complex FFT per pair of sequences.
 //
 // Layout of the complex FFT scratch: element m of sequence p lives at
 // z[m * ES + p] ("element-major"), ES >= P.  Consecutive threads take
@@ -53,6 +53,43 @@ __device__ __forceinline__ void dft8(cx<T> (&v)[8]) {
   v[7] = sub(e3, o3);
 }
 
+// Radix-16 DFT in place: with n = n2 + 4 n1 and k = k1 + 4 k2, radix-4 DFTs
+// over n1 for each n2, the twiddles w16^(n2 k1), then radix-4 DFTs over n2
+// for each k1.
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft16(cx<T> (&v)[16]) {
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173), r = T(0.70710678118654752440);
+  const T sg = T(SIGN);
+  cx<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = v[n2];
+    y[n2][1] = v[n2 + 4];
+    y[n2][2] = v[n2 + 8];
+    y[n2][3] = v[n2 + 12];
+    dft4<T, SIGN>(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
+  }
+  // w16^m = exp(SIGN 2 pi i m / 16) for m = n2 k1 in {1, 2, 3, 4, 6, 9}
+  y[1][1] = mul(y[1][1], mk(c1, sg * s1));
+  y[1][2] = mul(y[1][2], mk(r, sg * r));
+  y[1][3] = mul(y[1][3], mk(s1, sg * c1));
+  y[2][1] = mul(y[2][1], mk(r, sg * r));
+  y[2][2] = (SIGN < 0) ? mul_mi(y[2][2]) : mul_i(y[2][2]);
+  y[2][3] = mul(y[2][3], mk(-r, sg * r));
+  y[3][1] = mul(y[3][1], mk(s1, sg * c1));
+  y[3][2] = mul(y[3][2], mk(-r, sg * r));
+  y[3][3] = mul(y[3][3], mk(-c1, -sg * s1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a = y[0][k1], b = y[1][k1], c = y[2][k1], d = y[3][k1];
+    dft4<T, SIGN>(a, b, c, d);
+    v[k1] = a;
+    v[k1 + 4] = b;
+    v[k1 + 8] = c;
+    v[k1 + 12] = d;
+  }
+}
+
 // Twiddle accessors: exp(-2 pi i m / N) from a full table (each twiddle of
 // a butterfly read), or from two short tables as tw_hi[m / 32] * tw_lo[m % 32]
 // with the butterfly's other twiddles formed as powers of its first one
@@ -85,6 +122,10 @@ __device__ __forceinline__ void tw_powers(cx<T> (&w)[R], cx<T> w1) {
     w[6] = mul(w[3], w[3]);
     w[7] = mul(w[4], w[3]);
   }
+  if constexpr (R > 8) {
+#pragma unroll
+    for (int r = 8; r < R; ++r) w[r] = mul(w[r - 4], w[4]);
+  }
 }
 
 // Row of element m in the LDS buffer: with SKEW one padding row follows
@@ -107,7 +148,7 @@ __device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
   // first stage writes d = R t, d + r with r < R <= 8 in the same group of 8.
   constexpr int SRC = SKEW ? (N / R) + (N / R) / 8 : N / R;
   constexpr int DST = SKEW ? (Ns >= 8 ? Ns + Ns / 8 : 1) : Ns;
-  static_assert(!SKEW || Ns == 1 || Ns % 8 == 0, "stage strides");
+  static_assert(!SKEW || ((Ns == 1 && R <= 8) || Ns % 8 == 0), "stage strides");
   auto src_row = [](int t, int r) {
     if constexpr (!SKEW || (N / R) % 8 == 0) return zrow<SKEW>(t) + r * SRC;
     else return zrow<SKEW>(t + r * (N / R));
@@ -143,8 +184,10 @@ __device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
         v[i][1] = sub(a, b);
       } else if constexpr (R == 4) {
         dft4<T, SIGN>(v[i][0], v[i][1], v[i][2], v[i][3]);
-      } else {
+      } else if constexpr (R == 8) {
         dft8<T, SIGN>(v[i]);
+      } else {
+        dft16<T, SIGN>(v[i]);
       }
     }
   }
@@ -163,15 +206,19 @@ __device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
   __syncthreads();
 }
 
-// Complete FFT: radix-8 stages, then one radix-4 or radix-2 stage for the
-// remaining factor.  Input and output in natural order (Stockham autosort).
+// Complete FFT: radix-8 stages (radix-16 with R16, for a plain tile), then
+// one radix-4 or radix-2 stage for the remaining factor.  Input and output in
+// natural order (Stockham autosort).
 // Callers synchronize before the call (inputs written) and may read the
 // result right after it (the last stage ends with a barrier).
-template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW, int Ns, typename TW>
+template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW, int Ns, bool R16, typename TW>
 __device__ __forceinline__ void fft_stages_from(cx<T>* z, const TW& tw) {
-  if constexpr (Ns * 8 <= N) {
+  if constexpr (R16 && !SKEW && Ns * 16 <= N) {
+    fft_stage_tw<T, N, P, ES, NT, 16, SIGN, SKEW, Ns>(z, tw);
+    fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, Ns * 16, R16>(z, tw);
+  } else if constexpr (Ns * 8 <= N) {
     fft_stage_tw<T, N, P, ES, NT, 8, SIGN, SKEW, Ns>(z, tw);
-    fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, Ns * 8>(z, tw);
+    fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, Ns * 8, R16>(z, tw);
   } else if constexpr (Ns * 4 == N) {
     fft_stage_tw<T, N, P, ES, NT, 4, SIGN, SKEW, Ns>(z, tw);
   } else if constexpr (Ns * 2 == N) {
@@ -179,9 +226,9 @@ __device__ __forceinline__ void fft_stages_from(cx<T>* z, const TW& tw) {
   }
 }
 
-template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW = false, typename TW>
+template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW = false, bool R16 = false, typename TW>
 __device__ __forceinline__ void fft_lds_tw(cx<T>* z, const TW& tw) {
-  fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, 1>(z, tw);
+  fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, 1, R16>(z, tw);
 }
 
 template <typename T, int N, int P, int ES, int NT, int SIGN>
