@@ -148,7 +148,13 @@ __device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
   // first stage writes d = R t, d + r with r < R <= 8 in the same group of 8.
   constexpr int SRC = SKEW ? (N / R) + (N / R) / 8 : N / R;
   constexpr int DST = SKEW ? (Ns >= 8 ? Ns + Ns / 8 : 1) : Ns;
-  static_assert(!SKEW || ((Ns == 1 && R <= 8) || Ns % 8 == 0), "stage strides");
+  static_assert(!SKEW || Ns == 1 || Ns % 8 == 0, "stage strides");
+  // first stage with padding: d = R t is a multiple of 8, so row d + r sits
+  // r + r / 8 rows after row d
+  auto dst_off = [](int r) {
+    if constexpr (SKEW && Ns == 1) return r + (r >> 3);
+    else return r * DST;
+  };
   auto src_row = [](int t, int r) {
     if constexpr (!SKEW || (N / R) % 8 == 0) return zrow<SKEW>(t) + r * SRC;
     else return zrow<SKEW>(t + r * (N / R));
@@ -200,20 +206,20 @@ __device__ __forceinline__ void fft_stage_tw(cx<T>* z, const TW& tw) {
       const int k = t & (Ns - 1);
       const int d = (t - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[(zrow<SKEW>(d) + r * DST) * ES + p] = v[i][r];
+      for (int r = 0; r < R; ++r) z[(zrow<SKEW>(d) + dst_off(r)) * ES + p] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-// Complete FFT: radix-8 stages (radix-16 with R16, for a plain tile), then
-// one radix-4 or radix-2 stage for the remaining factor.  Input and output in
-// natural order (Stockham autosort).
+// Complete FFT: radix-8 stages (radix-16 with R16), then one radix-4 or
+// radix-2 stage for the remaining factor.  Input and output in natural order
+// (Stockham autosort).
 // Callers synchronize before the call (inputs written) and may read the
 // result right after it (the last stage ends with a barrier).
 template <typename T, int N, int P, int ES, int NT, int SIGN, bool SKEW, int Ns, bool R16, typename TW>
 __device__ __forceinline__ void fft_stages_from(cx<T>* z, const TW& tw) {
-  if constexpr (R16 && !SKEW && Ns * 16 <= N) {
+  if constexpr (R16 && Ns * 16 <= N) {
     fft_stage_tw<T, N, P, ES, NT, 16, SIGN, SKEW, Ns>(z, tw);
     fft_stages_from<T, N, P, ES, NT, SIGN, SKEW, Ns * 16, R16>(z, tw);
   } else if constexpr (Ns * 8 <= N) {

@@ -563,8 +563,8 @@ __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __
 // the twiddles as products of two short tables (indexed by m / 32 and
 // m mod 32), which leaves room for a third block per CU at N_t = 1024 than
 // the full table (measured 1.96 -> 1.69 ms at 512^2 x 1024).  In FP32 the
-// plain tile and the full table measured fastest, with radix-16 stages
-// (16 x 16 x 4 at N_t = 1024: 0.68 -> 0.65 ms; N_t = 256: 40 -> 36 us).
+// plain tile and the full table measured fastest.  Both use radix-16 stages
+// (16 x 16 x 4 at N_t = 1024: FP32 0.68 -> 0.65 ms, FP64 1.27 -> 1.16 ms).
 template <typename T, int NTT, int M, int NT>
 __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     }
   }
   __syncthreads();
-  fft_lds_tw<T, NTT, C, C, NT, -1, SK, !SK>(z, tws);
+  fft_lds_tw<T, NTT, C, C, NT, -1, SK, true>(z, tws);
   constexpr int WD = (NTT / 2 + 1) * C, ITD = cdiv_i(WD, NT);
   static_assert(NT % C == 0, "a thread keeps one mode pair c");
   // the mode pair of every item of this thread (NT is a multiple of C)
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     if (m != l) z[zrow<SK>(m) * C + c] = add(conj(y1), mul_i(conj(y2)));
   }
   __syncthreads();
-  fft_lds_tw<T, NTT, C, C, NT, +1, SK, !SK>(z, tws);
+  fft_lds_tw<T, NTT, C, C, NT, +1, SK, true>(z, tws);
   if constexpr (V2) {
 #pragma unroll
     for (int i = 0; i < IT2; ++i) {
