@@ -1162,7 +1162,8 @@ __global__ __launch_bounds__(256) void k_update_plain(double* __restrict__ U, co
 template <int DIM, int N>
 struct row_cfg {
   static constexpr int RB = DIM == 1 ? 4 : (N >= 512 ? 8 : (N >= 256 ? 16 : (N >= 32 ? 32 : N)));
-  static constexpr int NT0 = 256;
+  // 2D N >= 256: 512 threads (C5 inverse pass 0.944 -> 0.916 ms)
+  static constexpr int NT0 = (DIM == 2 && N >= 256) ? 512 : 256;
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
@@ -1185,7 +1186,10 @@ struct row_fwd_cfg {
 template <typename T, int N>
 struct col_cfg {
   static constexpr int XB = N < 32 ? N : ((sizeof(T) == 8 && N >= 256) ? 16 : 32);
-  static constexpr int NT = (N * XB / 2) < 256 ? (N * XB / 2) : 256;
+  // N >= 256: 512 threads (C5 mixed column passes 0.787 / 0.552 -> 0.764 /
+  // 0.541 ms)
+  static constexpr int NT0 = N >= 256 ? 512 : 256;
+  static constexpr int NT = (N * XB / 2) < NT0 ? (N * XB / 2) : NT0;
 };
 
 int rows_blocks_per_level(int dim, int n) {
