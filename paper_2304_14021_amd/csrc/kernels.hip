@@ -1397,7 +1397,9 @@ static hipError_t launch_time_m(T* S, const TimeArgs<T>& ta, hipStream_t st) {
   if constexpr (M > time_cfg<T, NTT>::MMAX || M < 2) {
     return hipErrorInvalidValue;
   } else {
-    PINT_LAUNCH((k_time_solve<T, NTT, M, 256>), dim3(ta.ns / M), dim3(256), 0, st, S, ta);
+    // FP32 at N_t >= 512: 512 threads (C5 0.645 -> 0.629 ms; FP64 slower)
+    constexpr int NTS = (sizeof(T) == 4 && NTT >= 512) ? 512 : 256;
+    PINT_LAUNCH((k_time_solve<T, NTT, M, NTS>), dim3(ta.ns / M), dim3(NTS), 0, st, S, ta);
     PINT_CHECK_LAUNCH();
     return hipSuccess;
   }
