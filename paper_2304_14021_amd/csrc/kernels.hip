@@ -1175,8 +1175,9 @@ struct row_fwd_cfg {
   // 256^2: half the inverse pass's height (8 rows; 16 measured slower); 512^2:
   // the full 8 rows (4 rows: 1171 us per launch at 512^2 x 1024, 8 rows: 1118 us)
   static constexpr int RB = (DIM == 2 && N == 256 && !WIDE) ? row_cfg<DIM, N>::RB / 2 : row_cfg<DIM, N>::RB;
-  // 2D N <= 128: 512 threads per block shorten each thread's serial chain
-  static constexpr int NT0 = (DIM == 2 && N >= 64) ? 512 : 256;
+  // 2D N >= 64: 512 threads per block shorten each thread's serial chain;
+  // 1024 at N = 512 (C5 mixed / FP64 1.34 / 1.36 -> 1.30 / 1.31 ms, FP32 the same)
+  static constexpr int NT0 = (DIM == 2 && N == 512) ? 1024 : ((DIM == 2 && N >= 64) ? 512 : 256);
   static constexpr int NT = RB * N < NT0 ? RB * N : NT0;
   static constexpr int NBL = DIM == 2 ? N / RB : 1;
 };
@@ -1186,9 +1187,9 @@ struct row_fwd_cfg {
 template <typename T, int N>
 struct col_cfg {
   static constexpr int XB = N < 32 ? N : ((sizeof(T) == 8 && N >= 256) ? 16 : 32);
-  // N >= 256: 512 threads (C5 mixed column passes 0.787 / 0.552 -> 0.764 /
-  // 0.541 ms)
-  static constexpr int NT0 = N >= 256 ? 512 : 256;
+  // N >= 256: 512 threads, N = 512: 1024 (C5 FP32 inverse pass 0.53 -> 0.49 ms,
+  // mixed forward / inverse 0.79 / 0.55 -> 0.74 / 0.50 ms)
+  static constexpr int NT0 = N >= 512 ? 1024 : (N >= 256 ? 512 : 256);
   static constexpr int NT = (N * XB / 2) < NT0 ? (N * XB / 2) : NT0;
 };
 
