@@ -231,9 +231,9 @@ const char* pint_plan_last_error(const pint_plan* plan);
 /* Bytes of device workspace pint_solve and the stage calls need: the
  * spectral array in the working type (N_t N_s values), a second one for 2D
  * plans on the FFT time path whose time-solve tile is narrower than a 128-byte
- * line (N_t >= 512: the iteration keeps that copy in panels, level-major per
- * panel of 32 FP32 / 16 FP64 modes), an FP64 copy for the mixed precision,
- * and the per-level partial sums and control record. */
+ * line (N_t >= 512: the iteration keeps that copy in panels of 32 modes, 16
+ * for FP64 and the mixed precision, level-major within a panel), an FP64 copy
+ * for the mixed precision, and the per-level partial sums and control record. */
 int pint_plan_workspace_size(const pint_plan* plan, size_t* bytes);
 /* alpha the plan uses (after automatic choice). */
 int pint_plan_alpha(const pint_plan* plan, double* alpha);
