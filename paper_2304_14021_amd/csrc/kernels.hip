@@ -275,6 +275,10 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
       a.part[size_t(slot) * PART_STRIDE + PART_RSQ] = rsq[q];
     }
   }
+  if (DIM == 2 && a.one_level) {
+    // level 0 stands for every level: its partial goes to each level's slot
+    for (int n = 1 + tid; n < a.nt; n += NT) a.part[(size_t(n) * NBL + b) * PART_STRIDE + PART_RSQ] = rsq[0];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -417,7 +421,7 @@ __device__ __forceinline__ size_t spec_off(int lev, int q, int tps, int nlev) {
 
 template <typename T, typename TO, int N, int XB, int NT, bool INV, bool PANEL>
 __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* __restrict__ done,
-                                              DctTables<T> dt, int tps) {
+                                              DctTables<T> dt, int tps, int nlev) {
   if (done && *done) return;
   constexpr int C = XB / 2, ES = C, NBX = N / XB, K = N / 2 + 1;
   __shared__ __align__(16) cx<T> z[N * ES];
@@ -434,7 +438,6 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
                                             : int(blockIdx.x);
   const int lev = blk / NBX;
   const int x0 = (blk - lev * NBX) * XB;
-  const int nlev = nb / NBX;
   // element (lev, q = row N + x); a pair (q, q + 1), q even, is contiguous in
   // both layouts
   const T* base = Sin + size_t(lev) * N * N + x0;
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W2 % NT == 0 || w < W2) {
         const int j = w / C2, c = w - (w / C2) * C2;
-        x[i] = *reinterpret_cast<const float4*>(Sb + j * rs + 4 * c);
+        x[i] = *reinterpret_cast<const float4*>(Sb + (ta.bcast_in ? 0 : j * rs) + 4 * c);
       }
     }
 #pragma unroll
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
       const int w = tid + i * NT;
       if (W % NT == 0 || w < W) {
         const int j = w / C, c = w - (w / C) * C;
-        x[i] = *reinterpret_cast<const cx<T>*>(Sb + j * rs + 2 * c);
+        x[i] = *reinterpret_cast<const cx<T>*>(Sb + (ta.bcast_in ? 0 : j * rs) + 2 * c);
       }
     }
 #pragma unroll
@@ -1230,7 +1233,8 @@ template <typename T, typename TO, int DIM, int N, bool WIDE, typename RT>
 static hipError_t launch_rows_fwd_w(const ResidArgs& a, TO* S, double* rout, const DctTables<T>& dt, int nt,
                                     int mode, hipStream_t st) {
   using C = row_fwd_cfg<DIM, N, WIDE>;
-  const int grid = DIM == 2 ? nt * C::NBL : nt / C::RB;
+  const int grid = DIM == 2 ? (a.one_level ? 1 : nt) * C::NBL : nt / C::RB;
+  if (a.one_level && (DIM != 2 || !a.bcast || a.nt != nt)) return hipErrorInvalidValue;
   if (mode == 0)
     PINT_LAUNCH((k_rows_fwd<T, TO, DIM, N, C::RB, C::NT, 0, RT>), dim3(grid), dim3(C::NT), 0, st, a, S,
                        rout, dt);
@@ -1274,9 +1278,13 @@ static hipError_t launch_rows_dct_n(const T* in, T* out, const DctTables<T>& dt,
 
 template <typename T, typename TO, int N>
 static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                                hipStream_t st, int tpi, int tpo) {
+                                hipStream_t st, int tpi, int tpo, int levels) {
   using C = col_cfg<T, N>;
-  const int grid = nt * (N / C::XB);
+  // levels: how many levels (from level 0) to transform, of the nt the
+  // layouts hold
+  if (levels < 0) levels = nt;
+  if (levels < 1 || levels > nt) return hipErrorInvalidValue;
+  const int grid = levels * (N / C::XB);
   // The plain side is [level][mode]; a panel of the spectral side holds whole
   // pairs of modes and at most one level's modes; in place only when plain.
   constexpr int PLAIN = 2 * ilog2(N);
@@ -1286,17 +1294,17 @@ static hipError_t launch_cols_n(const T* Sin, TO* Sout, const int* done, const D
   if (!inv) {
     if (tps == PLAIN)
       PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
-                  dt, tps);
+                  dt, tps, nt);
     else
       PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, false, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
-                  dt, tps);
+                  dt, tps, nt);
   } else if constexpr (std::is_same<T, TO>::value) {
     if (tps == PLAIN)
       PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true, false>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
-                  dt, tps);
+                  dt, tps, nt);
     else
       PINT_LAUNCH((k_cols<T, TO, N, C::XB, C::NT, true, true>), dim3(grid), dim3(C::NT), 0, st, Sin, Sout, done,
-                  dt, tps);
+                  dt, tps, nt);
   } else
     return hipErrorInvalidValue;
   PINT_CHECK_LAUNCH();
@@ -1343,8 +1351,8 @@ hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double*
 
 template <typename T, typename TO>
 hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                       hipStream_t st, int tps_in, int tps_out) {
-#define CC_(NN) launch_cols_n<T, TO, NN>(Sin, Sout, done, dt, nt, inv, st, tps_in, tps_out)
+                       hipStream_t st, int tps_in, int tps_out, int levels) {
+#define CC_(NN) launch_cols_n<T, TO, NN>(Sin, Sout, done, dt, nt, inv, st, tps_in, tps_out, levels)
   PINT_SWITCH_N(CC_)
 #undef CC_
 }
@@ -1575,11 +1583,11 @@ template hipError_t launch_rows_inv<float>(int, int, const UpdArgs&, const float
 template hipError_t launch_rows_inv<double>(int, int, const UpdArgs&, const double*, double*,
                                             const DctTables<double>&, int, int, hipStream_t);
 template hipError_t launch_cols<float, float>(int, const float*, float*, const int*, const DctTables<float>&, int,
-                                              bool, hipStream_t, int, int);
+                                              bool, hipStream_t, int, int, int);
 template hipError_t launch_cols<double, double>(int, const double*, double*, const int*, const DctTables<double>&,
-                                                int, bool, hipStream_t, int, int);
+                                                int, bool, hipStream_t, int, int, int);
 template hipError_t launch_cols<double, float>(int, const double*, float*, const int*, const DctTables<double>&,
-                                               int, bool, hipStream_t, int, int);
+                                               int, bool, hipStream_t, int, int, int);
 template hipError_t launch_dct<float>(int, int, const float*, float*, const DctTables<float>&, int, bool,
                                       hipStream_t);
 template hipError_t launch_dct<double>(int, int, const double*, double*, const DctTables<double>&, int, bool,

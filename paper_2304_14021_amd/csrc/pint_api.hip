@@ -462,6 +462,7 @@ void bind(const Offs& o, unsigned char* base, const pint_plan* pl, DctTables<T>&
   ta.done = nullptr;
   ta.tile = pl->time_tile;
   ta.tps = ilog2(pl->ns);
+  ta.bcast_in = 0;
 }
 
 struct Work {
@@ -576,6 +577,13 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
   ra.part = w.part;
   ra.done = &w.ctrl->done;
   ra.bcast = bcast ? 1 : 0;
+  // First sweep from the broadcast datum (2D, FFT time path): every level's
+  // residual and spatial transform are level 0's, so the row and column
+  // passes run on level 0 and the time solve reads it for every level.
+  const bool one = bcast && pl->dim == 2 && pl->dense < 0 && !pl->direct;
+  ra.one_level = one ? 1 : 0;
+  if (one) ra.nt = pl->nt;
+  ta.bcast_in = one ? 1 : 0;
   FinArgs fa{w.ctrl, host, w.part, w.fin, pl->nt, pl->nbl, pl->max_iter, pl->nbl_f, pl->norefine ? 1 : 0,
              pl->dof, pl->rtol, pl->safety};
   UpdArgs ua{d_U, d_u0, w.part, &w.ctrl->done, bcast ? 1 : 0, pl->norefine ? 1 : 0};
@@ -603,7 +611,8 @@ int enqueue_iteration(pint_plan* pl, const double* d_u0, double* d_U, const Work
            "residual + x-DCT kernel");
   if (pl->dim == 2) {
     ev(1);
-    HIPCHK((launch_cols<TF, T>(pl->n, SF, SP, done, dct_tables<TF>(pl), pl->nt, false, st, tpn, ta.tps)),
+    HIPCHK((launch_cols<TF, T>(pl->n, SF, SP, done, dct_tables<TF>(pl), pl->nt, false, st, tpn, ta.tps,
+                               one ? 1 : pl->nt)),
            "y-DCT kernel");
   }
   ev(2);

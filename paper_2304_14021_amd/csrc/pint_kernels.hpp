@@ -75,6 +75,9 @@ struct ResidArgs {
   const double* jfield;
   int wrap, nt;
   double wrap_alpha;
+  // With bcast in 2D every level's residual is the same: the launch covers
+  // level 0 only and its blocks write their partial sums for all nt levels.
+  int one_level;
 };
 
 struct FinArgs {
@@ -121,6 +124,7 @@ struct TimeArgs {
   int tile;           // cap on the spatial modes per workgroup (0 = automatic)
   int tps;            // log2 of the spectral panel width P: mode k of level n
                       // at ((k / P) N_t + n) P + k mod P (P = ns: [level][mode])
+  int bcast_in;       // every level's input is level 0's (read level 0 only)
 };
 
 struct InitArgs {
@@ -160,7 +164,7 @@ hipError_t launch_rows_inv(int dim, int n, const UpdArgs& a, const T* S, double*
 // TO == T and the two layouts are the same.
 template <typename T, typename TO>
 hipError_t launch_cols(int n, const T* Sin, TO* Sout, const int* done, const DctTables<T>& dt, int nt, bool inv,
-                       hipStream_t st, int tps_in, int tps_out);
+                       hipStream_t st, int tps_in, int tps_out, int levels = -1);
 // Spatial modes per workgroup of the FFT time solve (its panel width when
 // the spectral array is tiled).
 int time_tile_modes(bool fp64, int nt, int ns, int tile);
