@@ -35,9 +35,7 @@ BF16_ALPHA = 1e-2  # alpha of the BF16 runs (coarser contraction, larger alpha)
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain 256 MiB copy gives),
 # profiles/c5_fp32_hbm_traffic.md, c2_fp64_hbm_traffic.md, c2_mixed_hbm_traffic.md.
 # Valid for the kernel as measured: drop the entry when that kernel changes.
-MEASURED_TRAFFIC = {("c5", "fp32", "rows_fwd"): (1445477.0 * 2.0 + 1050624.0) * 1024,
-                    ("c2", "fp64", "rows_fwd"): (8759.7 * 2.0 + 16400.0) * 1024,
-                    ("c2", "mixed", "rows_fwd"): (11597.0 * 2.0 + 16400.0) * 1024}
+MEASURED_TRAFFIC = {}
 PREC_DESC = {
     "mixed": "FP64 residual, FP64 forward DCT, FP32 time FFT solve and inverse DCT, FP64 update "
              "(iterative refinement)",
@@ -86,7 +84,9 @@ HEADLINE = {"c2": ("fp64", 1e-6), "c3": ("mixed", 1e-4), "c5": ("fp32", 1e-4)}
 #   cols_inv  (y-DCT-III)           : read S (W)                      + write S (W)
 #   rows_inv  (x-DCT-III + update)  : read S (W) + read U (8)         + write U (8)
 # The first iteration starts from the broadcast datum: rows_fwd reads only u0
-# (N_s values) and rows_inv does not read U.
+# (N_s values) and rows_inv does not read U; in 2D its residual and spatial
+# transform are the same at every level, so rows_fwd and cols_fwd run on level
+# 0 only and the time solve reads that level for all N_t.
 STAGES = ["rows_fwd", "cols_fwd", "time_solve", "cols_inv", "rows_inv", "finalize"]
 KERNEL_NAMES = {"rows_fwd": "k_rows_fwd", "cols_fwd": "k_cols<fwd>", "time_solve": "k_time_solve",
                 "cols_inv": "k_cols<inv>", "rows_inv": "k_rows_inv"}
@@ -94,11 +94,13 @@ KERNEL_NAMES = {"rows_fwd": "k_rows_fwd", "cols_fwd": "k_cols<fwd>", "time_solve
 
 # Mixed precision: the forward transform is FP64 (rows_fwd writes 8 bytes,
 # cols_fwd reads 8 and writes 4), the rest FP32.
-def algo_bytes_per_dof(precision: str):
+def algo_bytes_per_dof(precision: str, dim: int = 1, nt: int = 1):
     w = 8 if precision == "fp64" else 4
     wf = 8 if precision in ("fp64", "mixed") else 4
     steady = {"rows_fwd": 8 + wf, "cols_fwd": wf + w, "time_solve": 2 * w, "cols_inv": 2 * w, "rows_inv": w + 16}
     first = dict(steady, rows_fwd=wf, rows_inv=w + 8)
+    if dim == 2:
+        first.update(rows_fwd=(8 + wf) / nt, cols_fwd=(wf + w) / nt, time_solve=w + w / nt)
     return steady, first
 
 
@@ -460,7 +462,7 @@ def main():
 
     # per-kernel average launch durations from the stage events (recorded on
     # the solve's stream around every launch of the timed region)
-    steady, first = algo_bytes_per_dof(args.precision)
+    steady, first = algo_bytes_per_dof(args.precision, p.dim, p.nt)
     tot_iters = sum(iters)
     avg_ms = {}
     for i, st in enumerate(STAGES):
