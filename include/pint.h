@@ -298,14 +298,16 @@ int pint_residual(pint_plan* plan, const double* d_u0, const double* d_U, double
 
 /* a2: orthonormal 2D (1D if dim = 1) DCT-II of each of the N_t slices of
  * d_in (type W, [N_t][N_y][N_x]) into d_out (type W, [N_t][k_y][k_x]);
- * d_in == d_out allowed.  inverse != 0 applies the inverse (DCT-III). */
+ * d_in == d_out allowed.  inverse != 0 applies the inverse (DCT-III).  Both
+ * buffers must be 16-byte aligned (PINT_EINVAL otherwise). */
 int pint_dct(pint_plan* plan, const void* d_in, void* d_out, int inverse, void* stream);
 
 /* a3-a5: for each spatial cosine mode k, y = Gamma^{-1} F^{-1} D^{-1} F Gamma x
  * over the time index: the alpha-circulant space-time solve in the DCT basis
  * (Section 2.1, eq. pintiter1 Steps 1-3; CH: eq. pintiter_CH), in place on
  * d_S (type W, [N_t][k_y][k_x]).  c_bar is the scalar averaged Jacobian used
- * by the CH operators (ignored for linear ones). */
+ * by the CH operators (ignored for linear ones).  d_S must be 16-byte aligned
+ * (PINT_EINVAL otherwise). */
 int pint_time_solve(pint_plan* plan, void* d_S, double c_bar, void* stream);
 
 /* a2-a6 without the update: d_delta = P_alpha^{-1} d_r for an FP64 residual

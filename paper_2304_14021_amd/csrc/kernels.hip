@@ -442,67 +442,144 @@ __global__ __launch_bounds__(NT) void k_cols(const T* Sin, TO* Sout, const int* 
   // both layouts
   const T* base = Sin + size_t(lev) * N * N + x0;
   TO* obase = Sout + size_t(lev) * N * N + x0;
+  // FP32 sides move two complex values (four columns, 16 bytes) per access
+  constexpr bool V2I = sizeof(T) == 4 && C % 2 == 0, V2O = sizeof(TO) == 4 && C % 2 == 0;
+  constexpr int C2 = C / 2;
   if (!INV) {
-    constexpr int W = N * C, IT = cdiv_i(W, NT);
-    cx<T> x[IT];
+    if constexpr (V2I) {
+      constexpr int W = N * C2, IT = cdiv_i(W, NT);
+      float4 x[IT];
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) {
-        const int m = w / C, c = w - (w / C) * C;
-        x[i] = *reinterpret_cast<const cx<T>*>(base + size_t(dct_perm<N>(m)) * N + 2 * c);
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (W % NT == 0 || w < W) {
+          const int m = w / C2, c = w - (w / C2) * C2;
+          x[i] = *reinterpret_cast<const float4*>(base + size_t(dct_perm<N>(m)) * N + 4 * c);
+        }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (W % NT == 0 || w < W) z[(w / C) * ES + (w - (w / C) * C)] = x[i];
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (W % NT == 0 || w < W) {
+          const int m = w / C2, c = w - (w / C2) * C2;
+          *reinterpret_cast<float4*>(z + m * ES + 2 * c) = x[i];
+        }
+      }
+    } else {
+      constexpr int W = N * C, IT = cdiv_i(W, NT);
+      cx<T> x[IT];
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (W % NT == 0 || w < W) {
+          const int m = w / C, c = w - (w / C) * C;
+          x[i] = *reinterpret_cast<const cx<T>*>(base + size_t(dct_perm<N>(m)) * N + 2 * c);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (W % NT == 0 || w < W) z[(w / C) * ES + (w - (w / C) * C)] = x[i];
+      }
     }
     __syncthreads();
     fft_lds<T, N, C, ES, NT, -1>(z, s_tw);
-    for (int w = tid; w < K * C; w += NT) {
-      const int k = w / C, c = w - (w / C) * C;
-      T x1k, x2k, x1n, x2n;
-      dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
-                 x1n, x2n);
-      *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev)) =
-          mk(TO(x1k), TO(x2k));
-      if (k > 0 && k < N / 2)
-        *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev)) =
-            mk(TO(x1n), TO(x2n));
-    }
-  } else {
-    constexpr int W = K * C, IT = cdiv_i(W, NT);
-    cx<T> xk[IT], xn[IT];
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      xk[i] = xn[i] = mk(T(0), T(0));
-      if (w < W) {
+    if constexpr (V2O) {
+      for (int w = tid; w < K * C2; w += NT) {
+        const int k = w / C2, c = 2 * (w - (w / C2) * C2);
+        const int kn = (N - k) & (N - 1);
+        T a1k, a2k, a1n, a2n, b1k, b2k, b1n, b2n;
+        dct2_split(z[k * ES + c], z[kn * ES + c], s_w[k], s_w[kn], a1k, a2k, a1n, a2n);
+        dct2_split(z[k * ES + c + 1], z[kn * ES + c + 1], s_w[k], s_w[kn], b1k, b2k, b1n, b2n);
+        *reinterpret_cast<float4*>(Sout + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev)) =
+            make_float4(float(a1k), float(a2k), float(b1k), float(b2k));
+        if (k > 0 && k < N / 2)
+          *reinterpret_cast<float4*>(Sout + spec_off<PANEL, N>(lev, kn * N + x0 + 2 * c, tps, nlev)) =
+              make_float4(float(a1n), float(a2n), float(b1n), float(b2n));
+      }
+    } else {
+      for (int w = tid; w < K * C; w += NT) {
         const int k = w / C, c = w - (w / C) * C;
-        xk[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev));
-        if (k) xn[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev));
+        T x1k, x2k, x1n, x2n;
+        dct2_split(z[k * ES + c], z[((N - k) & (N - 1)) * ES + c], s_w[k], s_w[(N - k) & (N - 1)], x1k, x2k,
+                   x1n, x2n);
+        *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev)) =
+            mk(TO(x1k), TO(x2k));
+        if (k > 0 && k < N / 2)
+          *reinterpret_cast<cx<TO>*>(Sout + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev)) =
+              mk(TO(x1n), TO(x2n));
       }
     }
-    __syncthreads();  // s_tw / s_w complete
+  } else {
+    if constexpr (V2I) {
+      constexpr int W = K * C2, IT = cdiv_i(W, NT);
+      float4 xk[IT], xn[IT];
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int w = tid + i * NT;
-      if (w < W) {
-        const int k = w / C, c = w - (w / C) * C;
-        cx<T> zk, zn;
-        dct3_join(xk[i].x, xk[i].y, xn[i].x, xn[i].y, s_w[k], zk, zn);
-        z[k * ES + c] = zk;
-        if (k > 0 && k < N / 2) z[(N - k) * ES + c] = zn;
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        xk[i] = xn[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (w < W) {
+          const int k = w / C2, c = 2 * (w - (w / C2) * C2);
+          xk[i] = *reinterpret_cast<const float4*>(Sin + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev));
+          if (k)
+            xn[i] = *reinterpret_cast<const float4*>(Sin + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev));
+        }
+      }
+      __syncthreads();  // s_tw / s_w complete
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (w < W) {
+          const int k = w / C2, c = 2 * (w - (w / C2) * C2);
+          cx<T> ak, an, bk, bn;
+          dct3_join(T(xk[i].x), T(xk[i].y), T(xn[i].x), T(xn[i].y), s_w[k], ak, an);
+          dct3_join(T(xk[i].z), T(xk[i].w), T(xn[i].z), T(xn[i].w), s_w[k], bk, bn);
+          *reinterpret_cast<float4*>(z + k * ES + c) = make_float4(ak.x, ak.y, bk.x, bk.y);
+          if (k > 0 && k < N / 2) *reinterpret_cast<float4*>(z + (N - k) * ES + c) = make_float4(an.x, an.y, bn.x, bn.y);
+        }
+      }
+    } else {
+      constexpr int W = K * C, IT = cdiv_i(W, NT);
+      cx<T> xk[IT], xn[IT];
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        xk[i] = xn[i] = mk(T(0), T(0));
+        if (w < W) {
+          const int k = w / C, c = w - (w / C) * C;
+          xk[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, k * N + x0 + 2 * c, tps, nlev));
+          if (k) xn[i] = *reinterpret_cast<const cx<T>*>(Sin + spec_off<PANEL, N>(lev, (N - k) * N + x0 + 2 * c, tps, nlev));
+        }
+      }
+      __syncthreads();  // s_tw / s_w complete
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int w = tid + i * NT;
+        if (w < W) {
+          const int k = w / C, c = w - (w / C) * C;
+          cx<T> zk, zn;
+          dct3_join(xk[i].x, xk[i].y, xn[i].x, xn[i].y, s_w[k], zk, zn);
+          z[k * ES + c] = zk;
+          if (k > 0 && k < N / 2) z[(N - k) * ES + c] = zn;
+        }
       }
     }
     __syncthreads();
     fft_lds<T, N, C, ES, NT, +1>(z, s_tw);
     const T inv_n = T(1) / T(N);
-    for (int w = tid; w < N * C; w += NT) {
-      const int m = w / C, c = w - (w / C) * C;
-      const cx<T> v = scale(z[m * ES + c], inv_n);
-      *reinterpret_cast<cx<TO>*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) = mk(TO(v.x), TO(v.y));
+    if constexpr (V2O) {
+      for (int w = tid; w < N * C2; w += NT) {
+        const int m = w / C2, c = 2 * (w - (w / C2) * C2);
+        const cx<T> v = scale(z[m * ES + c], inv_n), u = scale(z[m * ES + c + 1], inv_n);
+        *reinterpret_cast<float4*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) =
+            make_float4(float(v.x), float(v.y), float(u.x), float(u.y));
+      }
+    } else {
+      for (int w = tid; w < N * C; w += NT) {
+        const int m = w / C, c = w - (w / C) * C;
+        const cx<T> v = scale(z[m * ES + c], inv_n);
+        *reinterpret_cast<cx<TO>*>(obase + size_t(dct_perm<N>(m)) * N + 2 * c) = mk(TO(v.x), TO(v.y));
+      }
     }
   }
 }

@@ -1351,6 +1351,8 @@ int pint_residual(pint_plan* pl, const double* d_u0, const double* d_U, double* 
 
 int pint_dct(pint_plan* pl, const void* d_in, void* d_out, int inverse, void* stream) {
   if (!pl || !d_in || !d_out) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(d_in) | reinterpret_cast<uintptr_t>(d_out)) & 15)
+    return set_err(&pl->err, PINT_EINVAL, "DCT buffers must be 16-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (pl->fp64)
     HIPCHK(launch_dct<double>(pl->dim, pl->n, static_cast<const double*>(d_in), static_cast<double*>(d_out), pl->dtd,
@@ -1365,6 +1367,8 @@ int pint_dct(pint_plan* pl, const void* d_in, void* d_out, int inverse, void* st
 
 int pint_time_solve(pint_plan* pl, void* d_S, double c_bar, void* stream) {
   if (!pl || !d_S) return set_err(pl ? &pl->err : nullptr, PINT_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_S) & 15)
+    return set_err(&pl->err, PINT_EINVAL, "time-solve buffer must be 16-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (pl->fp64) {
