@@ -645,8 +645,18 @@ __global__ __launch_bounds__(NT) void k_rows_dct(const T* __restrict__ in, T* __
 // the full table (measured 1.96 -> 1.69 ms at 512^2 x 1024).  In FP32 the
 // plain tile and the full table measured fastest.  Both use radix-16 stages
 // (16 x 16 x 4 at N_t = 1024: FP32 0.68 -> 0.65 ms, FP64 1.27 -> 1.16 ms).
+// Minimum waves per SIMD asked of the compiler: the FP32 tile of 8 modes x
+// 1024 levels (40 KB of LDS) fits four 512-thread blocks per CU when the
+// kernel holds 64 registers (it takes 69 unconstrained, three blocks; no
+// spills at 64): C5 FP32 time solve 642 -> 609 us, mixed 574 -> 550 us.
+template <typename T, int NTT, int M>
+constexpr int time_solve_min_waves() {
+  return (sizeof(T) == 4 && NTT == 1024 && M == 8) ? 8 : 1;
+}
+
 template <typename T, int NTT, int M, int NT>
-__global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T> ta) {
+__global__ __launch_bounds__(NT, (time_solve_min_waves<T, NTT, M>())) void k_time_solve(T* __restrict__ S,
+                                                                                         TimeArgs<T> ta) {
   if (ta.done && *ta.done) return;
   constexpr int C = M / 2;
   constexpr bool F64 = sizeof(T) == 8;
@@ -741,10 +751,12 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
   const T lk1s = lk1 * lk1, lk2s = lk2 * lk2;
   const double cbd = ta.cbar_mode ? (ta.cbar ? *ta.cbar : ta.cbar_val) : 0.0;
   const T cb = T(cbd);
-  // the level coefficients of every item of this thread, loaded together
+  // FP64: the level coefficients of every item of this thread, loaded
+  // together (their latency was exposed otherwise); FP32 loads them where
+  // they are used, which saves registers (C3 256 x 32 tile: 130 -> 99)
   cx<T> l1v[ITD], plv[ITD], qlv[ITD];
 #pragma unroll
-  for (int i = 0; i < ITD; ++i) {
+  for (int i = 0; i < (F64 ? ITD : 0); ++i) {
     const int w = tid + i * NT;
     const int l = w < WD ? w / C : 0;
     l1v[i] = ta.lam1[l];
@@ -761,9 +773,9 @@ __global__ __launch_bounds__(NT) void k_time_solve(T* __restrict__ S, TimeArgs<T
     const cx<T> zm = conj(z[zrow<SK>(m) * C + c]);
     const cx<T> x1 = scale(add(zl, zm), T(0.5));
     const cx<T> x2 = scale(mul_mi(sub(zl, zm)), T(0.5));
-    const cx<T> l1 = l1v[i];
-    const cx<T> pl0 = plv[i];
-    const cx<T> ql = qlv[i];
+    const cx<T> l1 = F64 ? l1v[i] : ta.lam1[l];
+    const cx<T> pl0 = F64 ? plv[i] : ta.pco[l];
+    const cx<T> ql = F64 ? qlv[i] : ta.qco[l];
     const cx<T> pl = mk(pl0.x - cb, pl0.y);
     const cx<T> s1 = mk(l1.x + pl.x * lk1 + ql.x * lk1s, l1.y + pl.y * lk1 + ql.y * lk1s);
     const cx<T> s2 = mk(l1.x + pl.x * lk2 + ql.x * lk2s, l1.y + pl.y * lk2 + ql.y * lk2s);
