@@ -89,7 +89,9 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (a.done && *a.done) return;
   using Gm = rows_geom<DIM, N, RB>;
   constexpr int VR = Gm::VR, GR = Gm::GR, P = Gm::P, ES = Gm::ES, NBL = Gm::NBL;
-  constexpr int VB = VR * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
+  // 2D: v at RB + 2 rows per thread group of NT / N (see below); 1D: VR rows
+  constexpr int VROWS = DIM == 2 ? RB + 2 * (NT / N) : VR;
+  constexpr int VB = VROWS * N * int(sizeof(RT)), GB = GR * N * int(sizeof(RT)), ZB = N * ES * int(sizeof(cx<T>));
   constexpr int R0 = VB > ZB ? (VB > GB ? VB : GB) : (ZB > GB ? ZB : GB);
   constexpr int NV = DIM == 2 ? 1 : RB;
   // one buffer holds v, then g, then the packed DCT input (each phase keeps
@@ -113,135 +115,225 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   const double th = a.theta, omth = 1.0 - a.theta;
   const RT thr = RT(th), omr = RT(omth);
 
-  // Phase 1: v at positions y0-2 .. y0+RB+1 (clamped rows) -> V.  The own
-  // rows' time differences d = u_n - u_{n-1} stay in registers for phase 3
-  // (same point-to-thread map).  All loads are issued before any is used.
-  constexpr int HW = 2 * Gm::H * N, OW = RB * N;
-  constexpr int ITH = cdiv_i(HW, NT), ITO = cdiv_i(OW, NT);
-  RT d[ITO];
-  {
-    double hn[ITH > 0 ? ITH : 1], hm[ITH > 0 ? ITH : 1], on[ITO], om[ITO];
-#pragma unroll
-    for (int i = 0; i < ITH; ++i) {
-      const int w = tid + i * NT;
-      hn[i] = hm[i] = 0.0;
-      if (HW % NT == 0 || w < HW) {
-        const int hr = w / N, x = w - (w / N) * N;
-        const int vr = hr < Gm::H ? hr : hr + RB;
-        const int off = clampi(y0 - Gm::H + vr, N) * N + x;
-        if (bc) {
-          hn[i] = hm[i] = a.u0[off];
-        } else {
-          hn[i] = a.U[lev * ns + off];
-          // v = theta u_n + (1 - theta) u_{n-1}: no u_{n-1} halo for theta = 1
-          if (omth != 0.0) hm[i] = lev == 0 ? prev0(a, off, ns) : a.U[(lev - 1) * ns + off];
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < ITO; ++i) {
-      const int w = tid + i * NT;
-      on[i] = om[i] = 0.0;
-      if (OW % NT == 0 || w < OW) {
-        const int rr = w / N, x = w - (w / N) * N;
-        const int n = DIM == 2 ? lev : lev + rr;
-        const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-        if (bc) {
-          on[i] = om[i] = a.u0[off];
-        } else {
-          on[i] = a.U[n * ns + off];
-          om[i] = n == 0 ? prev0(a, off, ns) : a.U[(n - 1) * ns + off];
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < ITH; ++i) {
-      const int w = tid + i * NT;
-      if (HW % NT == 0 || w < HW) {
-        const int hr = w / N, x = w - (w / N) * N;
-        const int vr = hr < Gm::H ? hr : hr + RB;
-        V[vr * N + x] = thr * RT(hn[i]) + omr * RT(hm[i]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < ITO; ++i) {
-      const int w = tid + i * NT;
-      d[i] = RT(on[i]) - RT(om[i]);
-      if (OW % NT == 0 || w < OW) V[Gm::H * N + w] = thr * RT(on[i]) + omr * RT(om[i]);
-    }
-  }
-  __syncthreads();
-  // Phase 2: g at positions clamp(y0-1 .. y0+RB) -> registers -> G.
-  constexpr int GW = GR * N, ITG = cdiv_i(GW, NT);
-  RT gval[ITG];
-#pragma unroll
-  for (int i = 0; i < ITG; ++i) {
-    const int idx = tid + i * NT;
-    gval[i] = RT(0);
-    if (!(GW % NT == 0 || idx < GW)) continue;
-    const int gr = idx / N, x = idx - (idx / N) * N;
-    int c, yg = 0;
-    if (DIM == 2) {
-      yg = clampi(y0 - 1 + gr, N);
-      c = yg - (y0 - 2);  // V row holding position yg
-    } else {
-      c = gr;
-    }
-    const RT v = V[c * N + x];
-    RT lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - RT(2) * v;
-    if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - RT(2) * v;
-    const int goff = DIM == 2 ? yg * N + x : x;
-    // cubic term, or the averaged Jacobian field times v (linearized operator)
-    const RT nl = a.jfield ? RT(a.jfield[goff]) * v : RT(a.c3) * v * v * v;
-    RT g = nl + RT(a.c1) * v + RT(a.c2) * (lap * RT(a.inv_h2));
-    if (a.c1p != 0.0) {
-      const int n = DIM == 2 ? lev : lev + gr;
-      const RT um = RT(bc ? a.u0[goff] : (n == 0 ? prev0(a, goff, ns) : a.U[(n - 1) * ns + goff]));
-      g += RT(a.c1p) * um;
-    }
-    gval[i] = g;
-  }
-  __syncthreads();  // every v read
-#pragma unroll
-  for (int i = 0; i < ITG; ++i) {
-    const int idx = tid + i * NT;
-    if (GW % NT == 0 || idx < GW) G[idx] = gval[i];
-  }
-  __syncthreads();
-  // Phase 3: r on the own rows -> registers -> packed into z (same buffer).
   double rsq[NV];
-  RT rval[ITO];
 #pragma unroll
   for (int q = 0; q < NV; ++q) rsq[q] = 0.0;
+  if constexpr (DIM == 2) {
+    // Thread t owns column x = t mod N of rows yb .. yb+OR-1 (group t / N of
+    // the NT / N groups).  It holds that column's v at rows yb-2 .. yb+OR+1
+    // and g at yb-1 .. yb+OR in registers, so the stencils' vertical
+    // neighbours never leave the thread; the horizontal ones come from the
+    // group's LDS rows (v at yb-1 .. yb+OR, then g at yb .. yb+OR-1).
+    constexpr int GQ = NT / N, OR = RB / GQ, LR = OR + 2;
+    static_assert(NT % N == 0 && RB % GQ == 0, "whole rows per thread group");
+    const int x = tid & (N - 1), gq = tid / N;
+    const int yb = y0 + gq * OR;
+    const int xl = clampi(x - 1, N), xr = clampi(x + 1, N);
+    RT* Vg = V + gq * LR * N;  // row j (-1 .. OR) of the group at Vg[(j + 1) N]
+    const size_t lo = size_t(lev) * ns;
+    // All loads first: u_n at rows yb-2 .. yb+OR+1, u_{n-1} at the own rows
+    // and (theta < 1) at the four halo rows.  Level bases are uniform: u_n,
+    // and u_{n-1} = sm * Pm (the predecessor of level 0 is u0, or wrap_alpha
+    // u_{N_t} for the alpha-circulant operator); 32-bit offsets from them.
+    const double* Pn = bc ? a.u0 : a.U + lo;
+    const double* Pm = bc ? a.u0 : (lev > 0 ? a.U + lo - ns : (a.wrap ? a.U + size_t(a.nt - 1) * ns : a.u0));
+    const double sm = (!bc && lev == 0 && a.wrap) ? a.wrap_alpha : 1.0;
+    const bool halo_m = bc || omth != 0.0;
+    double un[OR + 4], um[OR], uh[4];
 #pragma unroll
-  for (int i = 0; i < ITO; ++i) {
-    const int w = tid + i * NT;
-    rval[i] = RT(0);
-    if (!(OW % NT == 0 || w < OW)) continue;
-    const int rr = w / N, x = w - (w / N) * N;
-    const int gc = DIM == 2 ? rr + 1 : rr;
-    const RT gv = G[gc * N + x];
-    RT lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - RT(2) * gv;
-    if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - RT(2) * gv;
-    const int nl = DIM == 2 ? lev : lev + rr;
-    const RT r = -d[i] * RT(a.inv_dts ? a.inv_dts[nl] : a.inv_dt) + lap * RT(a.inv_h2);
+    for (int j = 0; j < OR + 4; ++j) un[j] = Pn[unsigned(clampi(yb - 2 + j, N) * N + x)];
 #pragma unroll
-    for (int qq = 0; qq < NV; ++qq)
-      if (DIM == 2 || qq == rr) rsq[qq] += double(r) * double(r);
-    rval[i] = r;
-  }
-  __syncthreads();  // every g read
+    for (int i = 0; i < OR; ++i) um[i] = Pm[unsigned((yb + i) * N + x)];
 #pragma unroll
-  for (int i = 0; i < ITO; ++i) {
-    const int w = tid + i * NT;
-    if (!(OW % NT == 0 || w < OW)) continue;
-    const int rr = w / N, x = w - (w / N) * N;
-    if (MODE == 1) {
-      const int n = DIM == 2 ? lev : lev + rr;
-      const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-      rout[n * ns + off] = double(rval[i]);
-    } else {
-      comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(rval[i]);
+    for (int h = 0; h < 4; ++h)
+      uh[h] = halo_m ? Pm[unsigned(clampi(yb - 2 + (h < 2 ? h : OR + h), N) * N + x)] : 0.0;
+#pragma unroll
+    for (int i = 0; i < OR; ++i) um[i] *= sm;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) uh[h] *= sm;
+    RT v[OR + 4], d[OR];
+#pragma unroll
+    for (int j = 0; j < OR + 4; ++j) {
+      const int i = j - 2;
+      const double m = i < 0 ? uh[j] : (i >= OR ? uh[j - OR] : um[i]);
+      v[j] = thr * RT(un[j]) + omr * RT(m);
+    }
+#pragma unroll
+    for (int i = 0; i < OR; ++i) d[i] = RT(un[i + 2]) - RT(um[i]);
+#pragma unroll
+    for (int j = 1; j < OR + 3; ++j) Vg[(j - 1) * N + x] = v[j];
+    __syncthreads();
+    // g at rows yb-1 .. yb+OR; a row outside the grid takes the value of its
+    // reflection (the row inside), as the Neumann ghost of g
+    RT g[LR];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) {
+      const RT vc = v[j + 1];
+      RT lap = Vg[j * N + xl] + Vg[j * N + xr] - RT(2) * vc;
+      lap += v[j] + v[j + 2] - RT(2) * vc;
+      const int goff = clampi(yb - 1 + j, N) * N + x;
+      const RT nl = a.jfield ? RT(a.jfield[goff]) * vc : RT(a.c3) * vc * vc * vc;
+      RT gv = nl + RT(a.c1) * vc + RT(a.c2) * (lap * RT(a.inv_h2));
+      if (a.c1p != 0.0) {
+        const RT umg = RT(bc ? a.u0[goff] : (lev == 0 ? prev0(a, goff, ns) : a.U[lo - ns + goff]));
+        gv += RT(a.c1p) * umg;
+      }
+      g[j] = gv;
+      asm volatile("" ::: "memory");  // one row's LDS reads at a time (registers)
+    }
+    if (yb == 0) g[0] = g[1];
+    if (yb + OR == N) g[LR - 1] = g[LR - 2];
+    __syncthreads();  // every v read
+#pragma unroll
+    for (int i = 0; i < OR; ++i) Vg[(i + 1) * N + x] = g[i + 1];
+    __syncthreads();
+    RT rval[OR];
+    const RT idt = RT(a.inv_dts ? a.inv_dts[lev] : a.inv_dt);
+#pragma unroll
+    for (int i = 0; i < OR; ++i) {
+      const RT gc = g[i + 1];
+      RT lap = Vg[(i + 1) * N + xl] + Vg[(i + 1) * N + xr] - RT(2) * gc;
+      lap += g[i] + g[i + 2] - RT(2) * gc;
+      const RT r = -d[i] * idt + lap * RT(a.inv_h2);
+      rsq[0] += double(r) * double(r);
+      rval[i] = r;
+      asm volatile("" ::: "memory");
+    }
+    __syncthreads();  // every g read
+#pragma unroll
+    for (int i = 0; i < OR; ++i) {
+      const int rr = gq * OR + i;
+      if (MODE == 1) rout[lo + size_t(y0 + rr) * N + x] = double(rval[i]);
+      else comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(rval[i]);
+    }
+  } else {
+    // Phase 1: v at positions y0-2 .. y0+RB+1 (clamped rows) -> V.  The own
+    // rows' time differences d = u_n - u_{n-1} stay in registers for phase 3
+    // (same point-to-thread map).  All loads are issued before any is used.
+    constexpr int HW = 2 * Gm::H * N, OW = RB * N;
+    constexpr int ITH = cdiv_i(HW, NT), ITO = cdiv_i(OW, NT);
+    RT d[ITO];
+    {
+      double hn[ITH > 0 ? ITH : 1], hm[ITH > 0 ? ITH : 1], on[ITO], om[ITO];
+#pragma unroll
+      for (int i = 0; i < ITH; ++i) {
+        const int w = tid + i * NT;
+        hn[i] = hm[i] = 0.0;
+        if (HW % NT == 0 || w < HW) {
+          const int hr = w / N, x = w - (w / N) * N;
+          const int vr = hr < Gm::H ? hr : hr + RB;
+          const int off = clampi(y0 - Gm::H + vr, N) * N + x;
+          if (bc) {
+            hn[i] = hm[i] = a.u0[off];
+          } else {
+            hn[i] = a.U[lev * ns + off];
+            // v = theta u_n + (1 - theta) u_{n-1}: no u_{n-1} halo for theta = 1
+            if (omth != 0.0) hm[i] = lev == 0 ? prev0(a, off, ns) : a.U[(lev - 1) * ns + off];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < ITO; ++i) {
+        const int w = tid + i * NT;
+        on[i] = om[i] = 0.0;
+        if (OW % NT == 0 || w < OW) {
+          const int rr = w / N, x = w - (w / N) * N;
+          const int n = DIM == 2 ? lev : lev + rr;
+          const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+          if (bc) {
+            on[i] = om[i] = a.u0[off];
+          } else {
+            on[i] = a.U[n * ns + off];
+            om[i] = n == 0 ? prev0(a, off, ns) : a.U[(n - 1) * ns + off];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < ITH; ++i) {
+        const int w = tid + i * NT;
+        if (HW % NT == 0 || w < HW) {
+          const int hr = w / N, x = w - (w / N) * N;
+          const int vr = hr < Gm::H ? hr : hr + RB;
+          V[vr * N + x] = thr * RT(hn[i]) + omr * RT(hm[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < ITO; ++i) {
+        const int w = tid + i * NT;
+        d[i] = RT(on[i]) - RT(om[i]);
+        if (OW % NT == 0 || w < OW) V[Gm::H * N + w] = thr * RT(on[i]) + omr * RT(om[i]);
+      }
+    }
+    __syncthreads();
+    // Phase 2: g at positions clamp(y0-1 .. y0+RB) -> registers -> G.
+    constexpr int GW = GR * N, ITG = cdiv_i(GW, NT);
+    RT gval[ITG];
+#pragma unroll
+    for (int i = 0; i < ITG; ++i) {
+      const int idx = tid + i * NT;
+      gval[i] = RT(0);
+      if (!(GW % NT == 0 || idx < GW)) continue;
+      const int gr = idx / N, x = idx - (idx / N) * N;
+      int c, yg = 0;
+      if (DIM == 2) {
+        yg = clampi(y0 - 1 + gr, N);
+        c = yg - (y0 - 2);  // V row holding position yg
+      } else {
+        c = gr;
+      }
+      const RT v = V[c * N + x];
+      RT lap = V[c * N + clampi(x - 1, N)] + V[c * N + clampi(x + 1, N)] - RT(2) * v;
+      if (DIM == 2) lap += V[(c - 1) * N + x] + V[(c + 1) * N + x] - RT(2) * v;
+      const int goff = DIM == 2 ? yg * N + x : x;
+      // cubic term, or the averaged Jacobian field times v (linearized operator)
+      const RT nl = a.jfield ? RT(a.jfield[goff]) * v : RT(a.c3) * v * v * v;
+      RT g = nl + RT(a.c1) * v + RT(a.c2) * (lap * RT(a.inv_h2));
+      if (a.c1p != 0.0) {
+        const int n = DIM == 2 ? lev : lev + gr;
+        const RT um = RT(bc ? a.u0[goff] : (n == 0 ? prev0(a, goff, ns) : a.U[(n - 1) * ns + goff]));
+        g += RT(a.c1p) * um;
+      }
+      gval[i] = g;
+    }
+    __syncthreads();  // every v read
+#pragma unroll
+    for (int i = 0; i < ITG; ++i) {
+      const int idx = tid + i * NT;
+      if (GW % NT == 0 || idx < GW) G[idx] = gval[i];
+    }
+    __syncthreads();
+    // Phase 3: r on the own rows -> registers -> packed into z (same buffer).
+    RT rval[ITO];
+#pragma unroll
+    for (int i = 0; i < ITO; ++i) {
+      const int w = tid + i * NT;
+      rval[i] = RT(0);
+      if (!(OW % NT == 0 || w < OW)) continue;
+      const int rr = w / N, x = w - (w / N) * N;
+      const int gc = DIM == 2 ? rr + 1 : rr;
+      const RT gv = G[gc * N + x];
+      RT lap = G[gc * N + clampi(x - 1, N)] + G[gc * N + clampi(x + 1, N)] - RT(2) * gv;
+      if (DIM == 2) lap += G[(gc - 1) * N + x] + G[(gc + 1) * N + x] - RT(2) * gv;
+      const int nl = DIM == 2 ? lev : lev + rr;
+      const RT r = -d[i] * RT(a.inv_dts ? a.inv_dts[nl] : a.inv_dt) + lap * RT(a.inv_h2);
+#pragma unroll
+      for (int qq = 0; qq < NV; ++qq)
+        if (DIM == 2 || qq == rr) rsq[qq] += double(r) * double(r);
+      rval[i] = r;
+    }
+    __syncthreads();  // every g read
+#pragma unroll
+    for (int i = 0; i < ITO; ++i) {
+      const int w = tid + i * NT;
+      if (!(OW % NT == 0 || w < OW)) continue;
+      const int rr = w / N, x = w - (w / N) * N;
+      if (MODE == 1) {
+        const int n = DIM == 2 ? lev : lev + rr;
+        const int off = DIM == 2 ? (y0 + rr) * N + x : x;
+        rout[n * ns + off] = double(rval[i]);
+      } else {
+        comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) = T(rval[i]);
+      }
     }
   }
   __syncthreads();
