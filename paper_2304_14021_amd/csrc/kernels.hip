@@ -340,18 +340,18 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
   if (MODE == 0) {
     fft_lds<T, N, P, ES, NT, -1>(z, s_tw);
     constexpr int K = N / 2 + 1;
+    TO* const Sl = S + size_t(lev) * (DIM == 2 ? ns : size_t(N));  // uniform base, 32-bit offsets
     for (int w = tid; w < K * P; w += NT) {
       const int p = w / K, k = w - (w / K) * K;
       T x1k, x2k, x1n, x2n;
       dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
                  x1n, x2n);
-      const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
-      const size_t r1 = r0 + N;
-      S[r0 + k] = TO(x1k);
-      S[r1 + k] = TO(x2k);
+      const unsigned r0 = unsigned((DIM == 2 ? y0 + 2 * p : 2 * p) * N), r1 = r0 + N;
+      Sl[r0 + k] = TO(x1k);
+      Sl[r1 + k] = TO(x2k);
       if (k > 0 && k < N / 2) {
-        S[r0 + N - k] = TO(x1n);
-        S[r1 + N - k] = TO(x2n);
+        Sl[r0 + N - k] = TO(x1n);
+        Sl[r1 + N - k] = TO(x2n);
       }
     }
   }
@@ -396,6 +396,10 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
   const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
   constexpr int K = N / 2 + 1;
+  // this block's first level (uniform base): every offset below is 32-bit
+  const size_t lo = size_t(lev) * ns;
+  const T* Sl = S + (DIM == 2 ? lo : size_t(lev) * N);
+  double* Ul = a.U + lo;
   {
     constexpr int W = K * P, IT = cdiv_i(W, NT);
     T x1k[IT], x2k[IT], x1n[IT], x2n[IT];
@@ -405,13 +409,13 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
       x1k[i] = x2k[i] = x1n[i] = x2n[i] = T(0);
       if (w < W) {
         const int p = w / K, k = w - (w / K) * K;
-        const size_t r0 = DIM == 2 ? (size_t(lev) * N + y0 + 2 * p) * N : size_t(lev + 2 * p) * N;
-        const size_t r1 = r0 + N;
-        x1k[i] = S[r0 + k];
-        x2k[i] = S[r1 + k];
+        const unsigned r0 = unsigned((DIM == 2 ? y0 + 2 * p : 2 * p) * N);
+        const unsigned r1 = r0 + N;
+        x1k[i] = Sl[r0 + k];
+        x2k[i] = Sl[r1 + k];
         if (k) {
-          x1n[i] = S[r0 + N - k];
-          x2n[i] = S[r1 + N - k];
+          x1n[i] = Sl[r0 + N - k];
+          x2n[i] = Sl[r1 + N - k];
         }
       }
     }
@@ -446,9 +450,8 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         uo[q] = 0.0;
         if (MODE == 0 && i0 + q < IT && (W % NT == 0 || idx < W)) {
           const int rr = idx / N, x = idx - (idx / N) * N;
-          const int n = DIM == 2 ? lev : lev + rr;
           const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-          uo[q] = a.bcast ? a.u0[off] : a.U[n * ns + off];
+          uo[q] = a.bcast ? a.u0[unsigned(off)] : Ul[unsigned(DIM == 2 ? off : rr * int(ns) + x)];
         }
       }
 #pragma unroll
@@ -457,16 +460,14 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
         if (!(i0 + q < IT && (W % NT == 0 || idx < W))) continue;
         const int rr = idx / N, x = idx - (idx / N) * N;
         const double del = double(comp(z[dct_iperm<N>(x) * ES + (rr >> 1)], rr & 1) * inv_n);
-        const int n = DIM == 2 ? lev : lev + rr;
-        const int off = DIM == 2 ? (y0 + rr) * N + x : x;
-        const size_t gi = n * ns + off;
+        const unsigned gi = unsigned(DIM == 2 ? (y0 + rr) * N + x : rr * int(ns) + x);
         if (MODE == 1) {
-          dout[gi] = del;
+          dout[lo + gi] = del;
           continue;
         }
         // unrefined mode: the iterate is an FP32 quantity, updated in FP32
         const double u = a.round32 ? double(float(uo[q]) + float(del)) : uo[q] + del;
-        a.U[gi] = u;
+        Ul[gi] = u;
 #pragma unroll
         for (int qq = 0; qq < NV; ++qq) {
           if (DIM == 2 || qq == rr) {
