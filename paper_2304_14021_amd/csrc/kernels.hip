@@ -341,17 +341,25 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     fft_lds<T, N, P, ES, NT, -1>(z, s_tw);
     constexpr int K = N / 2 + 1;
     TO* const Sl = S + size_t(lev) * (DIM == 2 ? ns : size_t(N));  // uniform base, 32-bit offsets
-    for (int w = tid; w < K * P; w += NT) {
-      const int p = w / K, k = w - (w / K) * K;
-      T x1k, x2k, x1n, x2n;
-      dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
-                 x1n, x2n);
+    // items k = 0 .. N/2 - 1 of each sequence; the thread of k = 0 also takes
+    // k = N/2 (both pair with themselves), so no pass runs for a few lanes
+    constexpr int H = N / 2;
+    for (int w = tid; w < H * P; w += NT) {
+      const int p = w / H, k0 = w - (w / H) * H;
       const unsigned r0 = unsigned((DIM == 2 ? y0 + 2 * p : 2 * p) * N), r1 = r0 + N;
-      Sl[r0 + k] = TO(x1k);
-      Sl[r1 + k] = TO(x2k);
-      if (k > 0 && k < N / 2) {
-        Sl[r0 + N - k] = TO(x1n);
-        Sl[r1 + N - k] = TO(x2n);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (e == 1 && k0 != 0) break;
+        const int k = e ? H : k0;
+        T x1k, x2k, x1n, x2n;
+        dct2_split(z[k * ES + p], z[((N - k) & (N - 1)) * ES + p], s_wq[k], s_wq[(N - k) & (N - 1)], x1k, x2k,
+                   x1n, x2n);
+        Sl[r0 + k] = TO(x1k);
+        Sl[r1 + k] = TO(x2k);
+        if (k > 0 && k < H) {
+          Sl[r0 + N - k] = TO(x1n);
+          Sl[r1 + N - k] = TO(x2n);
+        }
       }
     }
   }
@@ -401,34 +409,42 @@ __global__ __launch_bounds__(NT) void k_rows_inv(UpdArgs a, const T* __restrict_
   const T* Sl = S + (DIM == 2 ? lo : size_t(lev) * N);
   double* Ul = a.U + lo;
   {
-    constexpr int W = K * P, IT = cdiv_i(W, NT);
+    // items k = 0 .. N/2 - 1 with their partners N - k; the thread of k = 0
+    // also takes k = N/2 (its own partner)
+    constexpr int H = N / 2, W = H * P, IT = cdiv_i(W, NT);
     T x1k[IT], x2k[IT], x1n[IT], x2n[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
       x1k[i] = x2k[i] = x1n[i] = x2n[i] = T(0);
-      if (w < W) {
-        const int p = w / K, k = w - (w / K) * K;
+      if (W % NT == 0 || w < W) {
+        const int p = w / H, k = w - (w / H) * H;
         const unsigned r0 = unsigned((DIM == 2 ? y0 + 2 * p : 2 * p) * N);
         const unsigned r1 = r0 + N;
         x1k[i] = Sl[r0 + k];
         x2k[i] = Sl[r1 + k];
-        if (k) {
-          x1n[i] = Sl[r0 + N - k];
-          x2n[i] = Sl[r1 + N - k];
-        }
+        // k = 0 has no partner: its second pair of values is row N/2's
+        x1n[i] = Sl[r0 + (k ? N - k : H)];
+        x2n[i] = Sl[r1 + (k ? N - k : H)];
       }
     }
     __syncthreads();  // s_tw / s_wi complete
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int w = tid + i * NT;
-      if (w < W) {
-        const int p = w / K, k = w - (w / K) * K;
+      if (W % NT == 0 || w < W) {
+        const int p = w / H, k = w - (w / H) * H;
         cx<T> zk, zn;
-        dct3_join(x1k[i], x2k[i], x1n[i], x2n[i], s_wi[k], zk, zn);
-        z[k * ES + p] = zk;
-        if (k > 0 && k < N / 2) z[(N - k) * ES + p] = zn;
+        if (k > 0) {
+          dct3_join(x1k[i], x2k[i], x1n[i], x2n[i], s_wi[k], zk, zn);
+          z[k * ES + p] = zk;
+          z[(N - k) * ES + p] = zn;
+        } else {
+          dct3_join(x1k[i], x2k[i], T(0), T(0), s_wi[0], zk, zn);
+          z[p] = zk;
+          dct3_join(x1n[i], x2n[i], x1n[i], x2n[i], s_wi[H], zk, zn);
+          z[H * ES + p] = zk;
+        }
       }
     }
   }
