@@ -76,8 +76,8 @@ template <int DIM, int N, int RB>
 struct rows_geom {
   static constexpr int NBL = DIM == 2 ? N / RB : 1;  // blocks per level
   static constexpr int H = DIM == 2 ? 2 : 0;         // v halo rows
-  static constexpr int VR = RB + 2 * H;              // v rows in LDS (positions y0-2 .. y0+RB+1)
-  static constexpr int GR = RB + (DIM == 2 ? 2 : 0); // g rows (positions y0-1 .. y0+RB)
+  static constexpr int VR = RB + 2 * H;              // v rows (positions y0-2 .. y0+RB+1; LDS rows in 1D)
+  static constexpr int GR = RB + (DIM == 2 ? 2 : 0); // g rows (positions y0-1 .. y0+RB; LDS rows in 1D)
   static constexpr int P = RB / 2;                   // packed complex sequences
   static constexpr int ES = P + 1;                   // odd stride of the complex scratch
 };
