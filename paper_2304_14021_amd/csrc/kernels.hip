@@ -107,7 +107,19 @@ __global__ __launch_bounds__(NT) void k_rows_fwd(ResidArgs a, TO* __restrict__ S
     table_to_lds<T, NT, N>(s_wq, dt.wq);
   }
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
+  // XCD strips: workgroup p runs on XCD p mod 8; each XCD takes a contiguous
+  // strip of NBL / 8 row blocks of every level, so halo rows shared by
+  // neighbouring blocks stay in one L2 (the previous level's block of the
+  // same rows already shares the XCD)
+  const int b = [] {
+    const int p = blockIdx.x;
+    if constexpr (DIM == 2 && NBL % 8 == 0) {
+      const int l = p / NBL, r = p - l * NBL;
+      return l * NBL + (r & 7) * (NBL / 8) + (r >> 3);
+    } else {
+      return p;
+    }
+  }();
   const int lev = DIM == 2 ? b / NBL : b * RB;
   const int y0 = DIM == 2 ? (b - (b / NBL) * NBL) * RB : 0;
   const size_t ns = DIM == 2 ? size_t(N) * N : size_t(N);
