@@ -125,6 +125,28 @@ def test_time_solve_stage(p, prec):
     assert err < tol, (err, tol)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_buffers_must_be_16_byte_aligned(prec):
+    """The DCT and time-solve stages move 16-byte pairs: a buffer 4 or 8
+    bytes off a 16-byte boundary is rejected with PINT_EINVAL before any
+    launch (the pointer is never dereferenced)."""
+    from paper_2304_14021_amd._pint import PINT_EINVAL, PintError
+    p = Problem(op="biharmonic", dim=2, n=16, nt=8, dt=1e-4, alpha=0.05)
+    say(f"stage alignment check {prec} {p}")
+    s = _solver(p, prec)
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    buf = torch.zeros(p.nt * p.ns + 4, dtype=tdt, device=dev())
+    base = buf.data_ptr()
+    assert base % 16 == 0
+    off = base + buf.element_size()  # 4 or 8 bytes past the boundary
+    for call in (lambda: s.plan.dct_raw(off, base, False), lambda: s.plan.dct_raw(base, off, True),
+                 lambda: s.plan.time_solve_raw(off, 0.0)):
+        with pytest.raises(PintError) as ei:
+            call()
+        assert ei.value.code == PINT_EINVAL
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 @pytest.mark.parametrize("p", CASES, ids=IDS)
 def test_precond_stage(p, prec):
